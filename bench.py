@@ -1,0 +1,164 @@
+"""Benchmark: 4-cycle-search edges/s of the HWPM weight-improvement rounds on one GPU.
+
+A step is one whole hwpm_improve call on the resident synthetic matrix: set-up
+(mates, matched weights, long-column table), every round of cycle search +
+per-root argmax (Steps A-C), conflict resolution (Step D) and flips, until a
+round flips nothing, then the fixed-order total and the output copy.  The
+inputs (CSC and the starting perfect matching) are in HBM before the timed
+region; the CSC is validated once, before it.
+
+value = nnz * rounds / (wall time per step)  [edges scanned per second]
+
+The JSON line also carries the roofline of the dominant kernel (the cycle
+search) from HIP events recorded by the library on its stream, and a CPU
+baseline: the oracle on the same workload on this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+
+
+def search_bytes(nnz: int, n: int, candidates: float) -> float:
+    """Algorithmic bytes of one cycle-search launch over the whole matrix:
+    every row index once (4 B/entry); per column col_ptr (8 B), its mate row,
+    the mate column of one row and the matched weight (4 + 4 + 8 B), and the
+    written Step-C flag (4 B); per root that keeps a cycle the winner record
+    (gain 8, other column 4, two positions 16, the Step-D slot 8, the list
+    entry 4 = 40 B)."""
+    return 4.0 * nnz + 28.0 * n + 40.0 * candidates
+
+
+def load_traffic(kernel: str):
+    """HBM bytes per launch measured by rocprofv3 counters, if recorded for the
+    current kernel source (profiles/traffic.json holds the source hash)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        import hashlib
+        with open(path) as f:
+            rec = json.load(f).get(kernel)
+        src = os.path.join(ROOT, "paper_1801_09809_amd", "csrc", "hwpm_kernels.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if rec and rec.get("kernel_src_sha") == sha:
+            return float(rec["bytes_per_launch"])
+    except Exception:
+        return None
+    return None
+
+
+def cpu_baseline(wl) -> dict:
+    """The oracle (single thread) on the same workload from the same matching."""
+    from oracle import oracle_improve
+    t0 = time.perf_counter()
+    ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
+    dt = time.perf_counter() - t0
+    return {"value": wl.nnz * ref.rounds / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"one full solve of {wl.name} ({ref.rounds} rounds, {dt:.2f} s)",
+            "rounds": ref.rounds}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=1)
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timing", action="store_true",
+                    help="skip the per-stage HIP events (roofline fields become null)")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_1801_09809_amd import hwpm
+    from workloads import workload
+
+    wl = workload(args.workload)
+    print(f"[bench] workload {args.workload}: {wl.name} n={wl.n} nnz={wl.nnz}", file=sys.stderr, flush=True)
+    dev = torch.device("cuda", 0)
+    cp = torch.from_numpy(wl.col_ptr).to(dev)
+    ri = torch.from_numpy(wl.row_idx).to(dev)
+    w = torch.from_numpy(wl.w).to(dev)
+    mate = torch.from_numpy(wl.planted).to(dev)
+    perm = torch.empty_like(mate)
+    solver = hwpm.Solver(0)
+    st = solver.check_csc(cp, ri, w)
+    if st != hwpm.HWPM_OK:
+        raise hwpm.HwpmError(st, "hwpm_check_csc")
+
+    def step():
+        return solver.improve(cp, ri, w, mate, perm_out=perm, check_csc=False,
+                              timing=not args.no_timing, tile_width=args.tile)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats.append(step().stats)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    rounds = stats[0]["rounds"]
+    assert all(s["rounds"] == rounds for s in stats)
+    edges = float(wl.nnz) * rounds
+    print(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step, rounds={rounds}", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": "4-cycle-search edges/s (1 GPU)",
+        "value": edges / (ms_step / 1e3),
+        "unit": "edges/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n": wl.n, "nnz": wl.nnz, "rounds": rounds,
+                   "cycles_applied": stats[0]["cycles_applied"],
+                   "start": "planted perfect matching (permuted diagonal)",
+                   "tile_width": args.tile or 16},
+    }
+    if not args.no_timing:
+        ms_search = float(np.mean([s["ms_search"] for s in stats]))
+        launch_ms = ms_search / rounds
+        cands = float(np.mean([np.mean(s["round_candidates"]) for s in stats]))
+        alg = search_bytes(wl.nnz, wl.n, cands)
+        achieved = alg / (launch_ms / 1e3) / 1e9
+        traffic = load_traffic("k_search_short")
+        out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "kernel": "k_search_short (Steps A-C)",
+                           "algorithmic_bytes_per_launch": alg, "avg_launch_ms": launch_ms}
+        out["search_edges_per_s"] = edges / (ms_search / 1e3)
+        out["ms_breakdown"] = {k: float(np.mean([s[k] for s in stats])) for k in
+                               ("ms_setup", "ms_search", "ms_resolve", "ms_apply", "ms_final", "ms_total")}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    solver.close()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

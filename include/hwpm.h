@@ -1,0 +1,180 @@
+/*
+ * hwpm.h -- heavy-weight perfect matching on one MI355X (gfx950).
+ *
+ * C ABI of libhwpm.so.  The library implements the weight-improvement phase
+ * of the heavy-weight perfect matching (HWPM) method of Azad, Buluc, Li,
+ * Wang and Langguth, "A distributed-memory algorithm for computing a
+ * heavy-weight perfect matching on bipartite graphs" (arXiv 1801.09809):
+ * bulk-synchronous rounds that find weight-increasing alternating 4-cycles,
+ * keep one per matched edge and flip a vertex-disjoint set of them
+ * (Section 5.3, Algorithms 2-6), repeated until no positive-gain 4-cycle is
+ * left.  Every step runs in hand-written HIP kernels; the host code only
+ * launches them and reads back a few counters per round.
+ *
+ * Problem (Section 3): an n x n sparse matrix A is the bipartite graph with
+ * row vertices R, column vertices C and one edge {i,j} of weight w(i,j) per
+ * nonzero a_ij.  A perfect matching pairs every column j with a distinct row
+ * m_j.  The caller supplies the weights; for static pivoting the paper uses
+ * w(i,j) = log|a_ij| (its "Option B": maximising the sum of logs maximises
+ * the product of the matched magnitudes) or |a_ij| ("Option A").
+ *
+ * Matrix layout (hwpm_csc): compressed sparse column, all DEVICE pointers.
+ *   col_ptr  int64[n+1]   col_ptr[0] = 0, nondecreasing, col_ptr[n] = nnz
+ *   row_idx  int32[nnz]   rows of column j at [col_ptr[j], col_ptr[j+1]),
+ *                         each in [0, n), strictly increasing in a column
+ *   weight   float64[nnz] finite
+ * Matchings are int32[n] arrays with perm[j] = the row matched to column j.
+ *
+ * Ownership: every buffer is owned by the caller, including the device
+ * workspace (hwpm_workspace_bytes tells its size).  The library allocates
+ * only a small pinned host buffer and a few HIP events, in hwpm_create.
+ *
+ * Streams: a handle is bound to one device and one HIP stream; all work is
+ * queued on that stream and every call returns when its results are ready.
+ * A handle is not thread-safe; calls on different handles may run
+ * concurrently if they use different workspaces.
+ *
+ * Errors: functions return HWPM_OK (0) or a negative status.  On any error
+ * the output arguments are left untouched.
+ *
+ * Results are deterministic: the same input gives bit-identical perm and
+ * total weight for every launch configuration, and equal those of the
+ * sequential round-by-round definition of the method (the CPU oracle in
+ * this repository).
+ */
+#ifndef HWPM_H
+#define HWPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define HWPM_OK          0
+#define HWPM_EINVAL     -1  /* bad argument: null pointer, negative size, bad option */
+#define HWPM_ESINGULAR  -2  /* the matrix has no perfect matching (Section 3) */
+#define HWPM_EBADCSC    -3  /* malformed CSC: col_ptr, row range, row order, non-finite weight */
+#define HWPM_EBADMATCH  -4  /* mate_in is not a perfect matching inside the pattern */
+#define HWPM_ENOMEM     -5  /* workspace smaller than hwpm_workspace_bytes() */
+#define HWPM_ETOOBIG    -6  /* n or nnz beyond the library limits (n < 2^31 - 1, nnz < 2^40) */
+#define HWPM_EDEVICE    -7  /* a HIP runtime call failed (no device, launch failure, ...) */
+#define HWPM_EINTERNAL  -8  /* an internal consistency check failed (a bug) */
+
+#define HWPM_MAX_ROUND_STATS 512
+
+typedef struct hwpm_handle_s* hwpm_handle;
+
+typedef struct {
+    int32_t n;               /* number of rows = number of columns, >= 0 */
+    int64_t nnz;             /* number of stored entries, >= 0 */
+    const int64_t* col_ptr;  /* device, n+1 */
+    const int32_t* row_idx;  /* device, nnz */
+    const double* weight;    /* device, nnz */
+} hwpm_csc;
+
+typedef struct {
+    /* Round cap (the paper's maxiters, Section 4 and Algorithm 2).
+     * 0 = repeat until a round applies no cycle (no positive-gain 4-cycle
+     * left).  >= 0. */
+    int32_t max_rounds;
+    /* 1 = validate the CSC on the device before solving (one pass over the
+     * matrix); 0 = the caller guarantees a well-formed CSC (e.g. it already
+     * passed hwpm_check_csc).  Kernels index with the given arrays, so a
+     * malformed CSC with check_csc = 0 is undefined behaviour. */
+    int32_t check_csc;
+    /* 1 = time every stage with HIP events into hwpm_stats (ms_*). */
+    int32_t timing;
+    /* Lanes per column in the cycle-search kernel: 0 = default, else one of
+     * 4, 8, 16, 32, 64.  Results do not depend on it. */
+    int32_t tile_width;
+} hwpm_options;
+
+typedef struct {
+    int32_t rounds;          /* search passes run (the last one finds no cycle unless capped) */
+    int32_t hit_round_cap;   /* 1 if max_rounds stopped the loop */
+    int64_t cycles_applied;  /* total 4-cycles flipped */
+    int32_t long_columns;    /* columns handled by the split (long-column) search */
+    int32_t reserved;
+    double init_weight;      /* total weight of mate_in (same summation order as the total) */
+    double final_weight;     /* = *total_out */
+    /* milliseconds, filled when options.timing = 1 (else 0) */
+    float ms_check;          /* CSC validation */
+    float ms_setup;          /* matching validation, mate/weight arrays, long-column table */
+    float ms_search;         /* Steps A-C (cycle search + per-root argmax), all rounds */
+    float ms_resolve;        /* Step D conflict resolution, all rounds */
+    float ms_apply;          /* flips, all rounds */
+    float ms_final;          /* total weight + output copy */
+    float ms_total;          /* whole call, host wall clock */
+    float ms_search_first;   /* Steps A-C of the first round alone */
+    /* per round (first HWPM_MAX_ROUND_STATS rounds) */
+    int32_t round_candidates[HWPM_MAX_ROUND_STATS]; /* roots that kept a cycle (Step C) */
+    int32_t round_applied[HWPM_MAX_ROUND_STATS];    /* cycles flipped (Step D) */
+    float round_ms_search[HWPM_MAX_ROUND_STATS];    /* Steps A-C time, when timing = 1 */
+} hwpm_stats;
+
+/* Fill *opt with the defaults: max_rounds 0, check_csc 1, timing 0,
+ * tile_width 0. */
+void hwpm_default_options(hwpm_options* opt);
+
+/* Text for a status code (static storage). */
+const char* hwpm_strerror(int status);
+
+/* Create a handle bound to HIP device `device` and HIP stream `stream`
+ * (a hipStream_t; NULL = the device's null stream).  Allocates a small
+ * pinned host buffer and HIP events.  Returns HWPM_EDEVICE if the device
+ * does not exist or HIP fails, HWPM_EINVAL if out is NULL. */
+int hwpm_create(hwpm_handle* out, int device, void* stream);
+
+/* Release a handle (waits for its stream).  NULL is accepted. */
+int hwpm_destroy(hwpm_handle h);
+
+/* Bytes of device workspace hwpm_improve / hwpm_check_csc need for an
+ * n x n matrix with nnz entries (a pure host computation).  The workspace
+ * must be 256-byte aligned (any hipMalloc / PyTorch allocation is). */
+int hwpm_workspace_bytes(int32_t n, int64_t nnz, size_t* bytes);
+
+/* Validate a CSC on the device: col_ptr[0] = 0, nondecreasing,
+ * col_ptr[n] = nnz, rows in [0, n) and strictly increasing within each
+ * column, weights finite.  Returns HWPM_OK or HWPM_EBADCSC. */
+int hwpm_check_csc(hwpm_handle h, const hwpm_csc* A, void* workspace, size_t workspace_bytes);
+
+/* Improve a perfect matching with weight-increasing alternating 4-cycles
+ * (Section 5.3).  One round:
+ *   Steps A+B  for every column j and every row i > m_j of column j, the
+ *              cycle (i, j, m_j, m_i) exists if the edge {m_j, m_i} does;
+ *              its gain (Section 3) is evaluated in binary64 as
+ *              (w(i,j) + w(m_j,m_i)) - (w(i,m_i) + w(m_j,j)); g > 0 makes it
+ *              a candidate;
+ *   Step C     each column j keeps its candidate of largest gain (equal
+ *              gains: smallest row i);
+ *   Step D     each column c = m_i accepts, unless c kept a cycle of its own,
+ *              the kept cycle of largest gain that uses its matched edge
+ *              (equal gains: smallest root column j); accepted cycles are
+ *              vertex-disjoint and all are flipped at once.
+ * Rounds repeat until one flips nothing, or max_rounds rounds ran.
+ *
+ *   mate_in    device int32[n]: a perfect matching contained in the pattern
+ *              (mate_in[j] = row of column j).  May alias perm_out.
+ *   perm_out   device int32[n]: the improved matching.
+ *   total_out  host, nullable: sum of the matched weights, added as a perfect
+ *              binary tree over columns 0..n-1 padded with +0.0 to a power
+ *              of two (pairs (2t, 2t+1) at each level).
+ *   opt        nullable (defaults).
+ *   stats      host, nullable.
+ *   workspace  device, >= hwpm_workspace_bytes(n, nnz) bytes; its contents
+ *              are scratch between calls.
+ * Errors: HWPM_EINVAL, HWPM_ENOMEM, HWPM_ETOOBIG, HWPM_EBADCSC (when
+ * opt->check_csc), HWPM_EBADMATCH, HWPM_EDEVICE, HWPM_EINTERNAL.
+ * n = 0 returns HWPM_OK with total 0.0. */
+int hwpm_improve(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
+                 double* total_out, const hwpm_options* opt, hwpm_stats* stats,
+                 void* workspace, size_t workspace_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWPM_H */

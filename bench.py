@@ -75,9 +75,14 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", type=int, default=1)
     ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--probe", type=int, default=0,
+                    help="0 default, 1 column search, 2 row lists, 3 chunked row lists")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timing", action="store_true",
                     help="skip the per-stage HIP events (roofline fields become null)")
+    ap.add_argument("--copy-calib-mib", type=int, default=0,
+                    help="after the timed steps, copy a buffer of this many MiB three times "
+                         "(a device copy kernel of known size, to scale rocprofv3 byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU layout is "
@@ -102,9 +107,10 @@ def main(argv=None) -> int:
     if st != hwpm.HWPM_OK:
         raise hwpm.HwpmError(st, "hwpm_check_csc")
 
-    def step():
-        return solver.improve(cp, ri, w, mate, perm_out=perm, check_csc=False,
-                              timing=not args.no_timing, tile_width=args.tile)
+    def step(full=True, timing=not args.no_timing):
+        # full rounds: every column searched every round (search throughput)
+        return solver.improve(cp, ri, w, mate, perm_out=perm, check_csc=False, timing=timing,
+                              tile_width=args.tile, probe=args.probe, full_search=full)
 
     for _ in range(args.warmup):
         step()
@@ -137,7 +143,7 @@ def main(argv=None) -> int:
         "config": {"workload": wl.name, "n": wl.n, "nnz": wl.nnz, "rounds": rounds,
                    "cycles_applied": stats[0]["cycles_applied"],
                    "start": "planted perfect matching (permuted diagonal)",
-                   "tile_width": args.tile or 16},
+                   "tile_width": args.tile or 4, "probe": args.probe or 3},
     }
     if not args.no_timing:
         ms_search = float(np.mean([s["ms_search"] for s in stats]))
@@ -148,11 +154,31 @@ def main(argv=None) -> int:
         traffic = load_traffic("k_search_short")
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                           "kernel": "k_search_short (Steps A-C)",
+                           "kernel": "k_search_chunk (Steps A-C)",
                            "algorithmic_bytes_per_launch": alg, "avg_launch_ms": launch_ms}
         out["search_edges_per_s"] = edges / (ms_search / 1e3)
         out["ms_breakdown"] = {k: float(np.mean([s[k] for s in stats])) for k in
-                               ("ms_setup", "ms_search", "ms_resolve", "ms_apply", "ms_final", "ms_total")}
+                               ("ms_setup", "ms_transpose", "ms_search", "ms_resolve", "ms_apply",
+                                "ms_final", "ms_total")}
+    # the library's default solve (incremental rounds: identical result)
+    if (args.probe or 3) == 3:
+        inc = [step(full=False, timing=False) for _ in range(max(2, args.warmup))]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = max(3, args.steps // 2)
+        for _ in range(reps):
+            inc_stats = step(full=False, timing=False).stats
+        torch.cuda.synchronize()
+        out["solve_ms_incremental"] = 1e3 * (time.perf_counter() - t1) / reps
+        out["incremental_roots_searched"] = int(sum(inc_stats["round_roots"]))
+        assert inc_stats["round_applied"] == stats[0]["round_applied"]
+    if args.copy_calib_mib:
+        src = torch.ones(args.copy_calib_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calib_bytes"] = src.numel() * 4
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
     solver.close()

@@ -90,6 +90,23 @@ typedef struct {
     /* Lanes per column in the cycle-search kernel: 0 = default, else one of
      * 4, 8, 16, 32, 64.  Results do not depend on it. */
     int32_t tile_width;
+    /* How the closing edge {m_j, m_i} is probed (results do not depend on it):
+     * 0 = default; 1 = binary search of row m_j in column m_i; 2 = build the
+     * pattern transpose once per call and test m_i against the row list of
+     * m_j (the marking trick of Section 4), with per-entry mate columns kept
+     * up to date across flips. */
+    int32_t probe;
+    /* Initial matching of hwpm_match (Section 5.2): 0 = heavy-edge tie-break
+     * in the greedy and BFS steps (the paper's heuristic, default);
+     * 1 = index order only (the paper's "without heuristic" ablation). */
+    int32_t mcm_plain;
+    /* 0 = incremental rounds (default with probe 3): after the first round
+     * only the columns whose cycles can have changed are searched again -- a
+     * flipped column, or a column holding a row whose mate changed; every
+     * other column keeps its Step-C winner, which is provably unchanged, so
+     * the results are identical.  1 = every round searches every column (the
+     * paper's rounds as written; the benchmark's search-throughput setting). */
+    int32_t full_search;
 } hwpm_options;
 
 typedef struct {
@@ -97,26 +114,35 @@ typedef struct {
     int32_t hit_round_cap;   /* 1 if max_rounds stopped the loop */
     int64_t cycles_applied;  /* total 4-cycles flipped */
     int32_t long_columns;    /* columns handled by the split (long-column) search */
-    int32_t reserved;
-    double init_weight;      /* total weight of mate_in (same summation order as the total) */
+    int32_t greedy_rounds;   /* hwpm_match: proposal rounds of the greedy step */
+    int32_t greedy_cardinality; /* hwpm_match: size of the greedy maximal matching */
+    int32_t mcm_cardinality; /* hwpm_match: size of the maximum matching */
+    int32_t mcm_phases;      /* hwpm_match: BFS phases that augmented */
+    int32_t mcm_levels;      /* hwpm_match: BFS levels over all phases */
+    double init_weight;      /* total weight of the starting perfect matching */
     double final_weight;     /* = *total_out */
-    /* milliseconds, filled when options.timing = 1 (else 0) */
+    /* milliseconds, filled when options.timing = 1 (else 0; ms_total always) */
     float ms_check;          /* CSC validation */
+    float ms_greedy;         /* hwpm_match: greedy maximal matching */
+    float ms_mcm;            /* hwpm_match: BFS phases */
     float ms_setup;          /* matching validation, mate/weight arrays, long-column table */
+    float ms_transpose;      /* pattern transpose + per-entry mate columns (probe >= 2) */
     float ms_search;         /* Steps A-C (cycle search + per-root argmax), all rounds */
     float ms_resolve;        /* Step D conflict resolution, all rounds */
-    float ms_apply;          /* flips, all rounds */
+    float ms_apply;          /* flips (and mate-column updates), all rounds */
     float ms_final;          /* total weight + output copy */
     float ms_total;          /* whole call, host wall clock */
     float ms_search_first;   /* Steps A-C of the first round alone */
+    float ms_reserved;
     /* per round (first HWPM_MAX_ROUND_STATS rounds) */
     int32_t round_candidates[HWPM_MAX_ROUND_STATS]; /* roots that kept a cycle (Step C) */
     int32_t round_applied[HWPM_MAX_ROUND_STATS];    /* cycles flipped (Step D) */
     float round_ms_search[HWPM_MAX_ROUND_STATS];    /* Steps A-C time, when timing = 1 */
+    int32_t round_roots[HWPM_MAX_ROUND_STATS];      /* columns searched */
 } hwpm_stats;
 
 /* Fill *opt with the defaults: max_rounds 0, check_csc 1, timing 0,
- * tile_width 0. */
+ * tile_width 0, probe 0, mcm_plain 0, full_search 0. */
 void hwpm_default_options(hwpm_options* opt);
 
 /* Text for a status code (static storage). */
@@ -172,6 +198,27 @@ int hwpm_check_csc(hwpm_handle h, const hwpm_csc* A, void* workspace, size_t wor
 int hwpm_improve(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
                  double* total_out, const hwpm_options* opt, hwpm_stats* stats,
                  void* workspace, size_t workspace_bytes);
+
+/* The whole HWPM pipeline (Section 5.1): a greedy maximal matching, then a
+ * maximum-cardinality matching by multi-source BFS phases (both with the
+ * heavy-edge tie-break of Section 5.2 unless opt->mcm_plain), then the rounds
+ * of hwpm_improve.
+ *   Greedy    rounds of proposals: every unmatched column proposes to its
+ *             unmatched row of largest weight (ties: smallest row); a row with
+ *             proposals accepts the heaviest (ties: smallest column); until no
+ *             unmatched column has an unmatched neighbour.
+ *   BFS phase every unmatched column roots a tree; each level, every row not
+ *             yet visited that is adjacent to a frontier column joins the tree
+ *             of its heaviest such column (ties: smallest column); a tree that
+ *             reaches unmatched rows keeps the smallest one and stops; the
+ *             mates of the level's matched rows of growing trees form the next
+ *             frontier; at the end every recorded path is augmented.  Phases
+ *             repeat until one augments nothing.
+ *   perm_out  device int32[n]; total_out as in hwpm_improve.
+ * Returns HWPM_ESINGULAR when the maximum matching is not perfect (outputs
+ * untouched), else as hwpm_improve. */
+int hwpm_match(hwpm_handle h, const hwpm_csc* A, int32_t* perm_out, double* total_out,
+               const hwpm_options* opt, hwpm_stats* stats, void* workspace, size_t workspace_bytes);
 
 #ifdef __cplusplus
 }

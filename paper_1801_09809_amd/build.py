@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhwpm.so")
-SOURCES = ["hwpm_api.hip", "hwpm_kernels.hip"]
+SOURCES = ["hwpm_api.hip", "hwpm_kernels.hip", "hwpm_mcm.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -20,7 +20,8 @@ struct hwpm_handle_s {
 
 namespace {
 
-constexpr int kDefaultTile = 16;
+constexpr int kDefaultTile = 4;
+constexpr int kDefaultProbe = 3;
 constexpr int32_t kLongThreshold = 256;   // longer columns use the split search
 constexpr int64_t kMaxNnz = (int64_t)1 << 40;
 
@@ -77,6 +78,210 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+// The rounds of Section 5.3 from the perfect matching mate_in (CSC already
+// validated or trusted).  Fills the round statistics of *Sp.
+int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_in,
+                int32_t* perm_out, double* total_out, const hwpm_options& opt, hwpm_stats* Sp) {
+    hwpm_stats& S = *Sp;
+    const int32_t n = A.n;
+    hipStream_t s = h->stream;
+    const bool timing = opt.timing != 0;
+    hipEvent_t* ev = h->ev;
+    const int tile = opt.tile_width ? opt.tile_width : kDefaultTile;
+    const int probe = opt.probe ? opt.probe : kDefaultProbe;
+    const bool transposed = probe >= 2;
+    const bool incremental = probe == 3 && !opt.full_search;
+    // 2. set-up: mates, matched weights, matching validation, long columns
+    if (timing) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(hipMemsetAsync(W.counters, 0, kCounterWords * sizeof(int32_t), s));
+    HIP_TRY(hipMemsetAsync(W.mr, 0xff, (size_t)n * sizeof(int32_t), s));
+    HIP_TRY(launch_init_match(A, W, mate_in, kLongThreshold, s));
+    HIP_TRY(launch_long_chunks(W, A, s));
+    HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[1], s));
+    HIP_TRY(hipMemcpyAsync(h->host, W.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->host + 8, &W.result[1], sizeof(double), hipMemcpyDeviceToHost, s));
+    if (timing) HIP_TRY(hipEventRecord(ev[1], s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (timing) S.ms_setup = elapsed(ev[0], ev[1]);
+    if (h->host[kErrMatch]) return HWPM_EBADMATCH;
+    const int32_t n_long = h->host[kNumLong];
+    S.long_columns = n_long;
+    memcpy(&S.init_weight, h->host + 8, sizeof(double));
+    if (transposed) {
+        if (timing) HIP_TRY(hipEventRecord(ev[0], s));
+        if (incremental) HIP_TRY(hipMemsetAsync(W.dirty, 0, (size_t)n * sizeof(int32_t), s));
+        HIP_TRY(launch_transpose(A, W, kLongThreshold, n_long > 0, s, h->cus));
+        if (timing) {
+            HIP_TRY(hipEventRecord(ev[1], s));
+            HIP_TRY(hipEventSynchronize(ev[1]));
+            S.ms_transpose = elapsed(ev[0], ev[1]);
+        }
+    }
+
+    // 3. rounds.  In incremental mode the first round searches every root and
+    // later rounds only the roots the previous flips touched (the others keep
+    // their Step-C records, which cannot have changed).
+    int32_t round = 0;
+    int32_t nroots = n;
+    for (;;) {
+        if (opt.max_rounds > 0 && round >= opt.max_rounds) {
+            S.hit_round_cap = 1;
+            break;
+        }
+        const int slot = round % kSlots;
+        const bool listed = incremental && round > 0;
+        if (timing) HIP_TRY(hipEventRecord(ev[2], s));
+        if (!listed || nroots > 0)
+            HIP_TRY(launch_search(A, W, tile, kLongThreshold, slot, n_long > 0, probe,
+                                  listed ? W.dirty_list : nullptr, nroots, incremental, s, h->cus));
+        HIP_TRY(launch_collect(A, W, slot, s, h->cus));
+        if (timing) HIP_TRY(hipEventRecord(ev[3], s));
+        HIP_TRY(launch_resolve(W, slot, s, h->cus));
+        if (timing) HIP_TRY(hipEventRecord(ev[4], s));
+        HIP_TRY(launch_apply(A, W, slot, transposed, s, h->cus));
+        if (transposed) HIP_TRY(launch_mrk_update(W, slot, incremental, s, h->cus));
+        if (timing) HIP_TRY(hipEventRecord(ev[5], s));
+        HIP_TRY(hipMemcpyAsync(h->host, W.counters + slot_word(slot, 0), kSlotWords * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h->host + kSlotWords, W.counters + slot_word((slot + 1) % kSlots, 0),
+                               kSlotWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const int32_t n_cand = h->host[kCand], n_applied = h->host[kApplied];
+        if (round < HWPM_MAX_ROUND_STATS) {
+            S.round_candidates[round] = n_cand;
+            S.round_applied[round] = n_applied;
+            S.round_roots[round] = nroots;
+        }
+        nroots = incremental ? h->host[kSlotWords + kRoots] : n;
+        if (timing) {
+            const float ms = elapsed(ev[2], ev[3]);
+            S.ms_search += ms;
+            if (round == 0) S.ms_search_first = ms;
+            if (round < HWPM_MAX_ROUND_STATS) S.round_ms_search[round] = ms;
+            S.ms_resolve += elapsed(ev[3], ev[4]);
+            S.ms_apply += elapsed(ev[4], ev[5]);
+        }
+        S.cycles_applied += n_applied;
+        ++round;
+        // A round with candidates always flips at least one cycle (the
+        // candidate whose other column has the largest matched row).
+        if (n_cand > 0 && n_applied == 0) return HWPM_EINTERNAL;
+        if (n_applied == 0) break;
+    }
+    S.rounds = round;
+
+    // 4. outputs
+    if (timing) HIP_TRY(hipEventRecord(ev[6], s));
+    HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[0], s));
+    HIP_TRY(hipMemcpyAsync(perm_out, W.mc, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(h->host + 8, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
+    if (timing) HIP_TRY(hipEventRecord(ev[7], s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (timing) S.ms_final = elapsed(ev[6], ev[7]);
+    double total;
+    memcpy(&total, h->host + 8, sizeof(double));
+    S.final_weight = total;
+    *total_out = total;
+    return HWPM_OK;
+}
+
+int timed_check(hwpm_handle h, const Csc& A, const Work& W, bool timing, hwpm_stats* S) {
+    hipEvent_t* ev = h->ev;
+    if (timing) HIP_TRY(hipEventRecord(ev[0], h->stream));
+    const int st = run_check(h, A, W);
+    if (st != HWPM_OK) return st;
+    if (timing) {
+        HIP_TRY(hipEventRecord(ev[1], h->stream));
+        HIP_TRY(hipEventSynchronize(ev[1]));
+        S->ms_check = elapsed(ev[0], ev[1]);
+    }
+    return HWPM_OK;
+}
+
+int check_options(const hwpm_options& opt) {
+    if (opt.max_rounds < 0) return HWPM_EINVAL;
+    const int tile = opt.tile_width ? opt.tile_width : kDefaultTile;
+    if (tile != 4 && tile != 8 && tile != 16 && tile != 32 && tile != 64) return HWPM_EINVAL;
+    const int probe = opt.probe ? opt.probe : kDefaultProbe;
+    if (probe < 1 || probe > 3) return HWPM_EINVAL;
+    if (probe == 3 && tile == 64) return HWPM_EINVAL;
+    if (opt.mcm_plain != 0 && opt.mcm_plain != 1) return HWPM_EINVAL;
+    if (opt.full_search != 0 && opt.full_search != 1) return HWPM_EINVAL;
+    return HWPM_OK;
+}
+
+// Phase I (Sections 5.1-5.2): greedy proposal rounds, then BFS phases until
+// no augmenting path is found.  Leaves a perfect matching in M.mc, or returns
+// HWPM_ESINGULAR.
+int run_initial_matching(hwpm_handle h, const Csc& A, const Work& W, const Mcm& M, int heavy,
+                         bool timing, hwpm_stats* S) {
+    hipStream_t s = h->stream;
+    hipEvent_t* ev = h->ev;
+    int32_t* host = h->host;
+    if (timing) HIP_TRY(hipEventRecord(ev[0], s));
+    HIP_TRY(hipMemsetAsync(W.counters, 0, kCounterWords * sizeof(int32_t), s));
+    HIP_TRY(launch_mcm_init(A, M, W, kLongThreshold, s, h->cus));
+    HIP_TRY(hipMemcpyAsync(host, W.counters + kNumLong, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    const bool has_long = host[0] > 0;
+    int32_t rounds = 0;
+    for (;;) {
+        HIP_TRY(hipMemsetAsync(M.counters, 0, kMcmWords * sizeof(int32_t), s));
+        HIP_TRY(launch_greedy_round(A, M, W, heavy, kLongThreshold, has_long, s, h->cus));
+        HIP_TRY(hipMemcpyAsync(host, M.counters, kMcmWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        ++rounds;
+        if (host[kMcmProposals] == 0) break;
+    }
+    S->greedy_rounds = rounds;
+    if (timing) {
+        HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(hipEventSynchronize(ev[1]));
+        S->ms_greedy = elapsed(ev[0], ev[1]);
+        HIP_TRY(hipEventRecord(ev[0], s));
+    }
+    int32_t phases = 0, levels = 0, unmatched = 0;
+    bool first = true;
+    for (;;) {
+        HIP_TRY(hipMemsetAsync(M.counters, 0, kMcmWords * sizeof(int32_t), s));
+        HIP_TRY(launch_bfs_roots(A, M, s, h->cus));
+        HIP_TRY(hipMemcpyAsync(host, M.counters, kMcmWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        unmatched = host[kMcmFrontier];
+        if (first) {
+            S->greedy_cardinality = A.n - unmatched;
+            first = false;
+        }
+        if (unmatched == 0) break;
+        ++phases;
+        int32_t nf = unmatched;
+        int32_t* cur = M.front_a;
+        int32_t* nxt = M.front_b;
+        while (nf > 0) {
+            HIP_TRY(launch_bfs_level(A, M, cur, nf, nxt, heavy, s, h->cus));
+            HIP_TRY(hipMemcpyAsync(host, M.counters, kMcmWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            ++levels;
+            nf = host[kMcmNext];
+            HIP_TRY(hipMemsetAsync(M.counters + kMcmNext, 0, 2 * sizeof(int32_t), s));  // next, level
+            int32_t* t = cur; cur = nxt; nxt = t;
+        }
+        HIP_TRY(launch_bfs_augment(A, M, s, h->cus));
+        HIP_TRY(hipMemcpyAsync(host, M.counters, kMcmWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (host[kMcmAugmented] == 0) break;  // no augmenting path: maximum reached
+    }
+    S->mcm_phases = phases;
+    S->mcm_levels = levels;
+    S->mcm_cardinality = A.n - unmatched;
+    if (timing) {
+        HIP_TRY(hipEventRecord(ev[1], s));
+        HIP_TRY(hipEventSynchronize(ev[1]));
+        S->ms_mcm = elapsed(ev[0], ev[1]);
+    }
+    return unmatched == 0 ? HWPM_OK : HWPM_ESINGULAR;
+}
+
 }  // namespace
 
 extern "C" {
@@ -87,6 +292,9 @@ void hwpm_default_options(hwpm_options* opt) {
     opt->check_csc = 1;
     opt->timing = 0;
     opt->tile_width = 0;
+    opt->probe = 0;
+    opt->mcm_plain = 0;
+    opt->full_search = 0;
 }
 
 const char* hwpm_strerror(int status) {
@@ -172,9 +380,8 @@ int hwpm_improve(hwpm_handle h, const hwpm_csc* Ain, const int32_t* mate_in, int
     hwpm_options opt;
     hwpm_default_options(&opt);
     if (opt_in) opt = *opt_in;
-    if (opt.max_rounds < 0) return HWPM_EINVAL;
-    int tile = opt.tile_width ? opt.tile_width : kDefaultTile;
-    if (tile != 4 && tile != 8 && tile != 16 && tile != 32 && tile != 64) return HWPM_EINVAL;
+    st = check_options(opt);
+    if (st != HWPM_OK) return st;
     const int32_t n = Ain->n;
     if (n > 0 && (!mate_in || !perm_out)) return HWPM_EINVAL;
     const size_t need = workspace_layout(n, Ain->nnz, nullptr, nullptr);
@@ -193,90 +400,59 @@ int hwpm_improve(hwpm_handle h, const hwpm_csc* Ain, const int32_t* mate_in, int
     const Csc A = to_csc(Ain);
     Work W;
     workspace_layout(n, A.nnz, (char*)workspace, &W);
-    hipStream_t s = h->stream;
-    const bool timing = opt.timing != 0;
-    hipEvent_t* ev = h->ev;
-
-    // 1. optional CSC validation
     if (opt.check_csc) {
-        if (timing) HIP_TRY(hipEventRecord(ev[0], s));
-        st = run_check(h, A, W);
+        st = timed_check(h, A, W, opt.timing != 0, &S);
         if (st != HWPM_OK) return st;
-        if (timing) {
-            HIP_TRY(hipEventRecord(ev[1], s));
-            HIP_TRY(hipEventSynchronize(ev[1]));
-            S.ms_check = elapsed(ev[0], ev[1]);
-        }
     }
+    double total = 0.0;
+    st = run_improve(h, A, W, mate_in, perm_out, &total, opt, &S);
+    if (st != HWPM_OK) return st;
+    if (total_out) *total_out = total;
+    S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
+    if (stats) *stats = S;
+    return HWPM_OK;
+}
 
-    // 2. set-up: mates, matched weights, matching validation, long columns
-    if (timing) HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(hipMemsetAsync(W.counters, 0, kCounterWords * sizeof(int32_t), s));
-    HIP_TRY(hipMemsetAsync(W.mr, 0xff, (size_t)n * sizeof(int32_t), s));
-    HIP_TRY(launch_init_match(A, W, mate_in, kLongThreshold, s));
-    HIP_TRY(launch_long_chunks(W, A, s));
-    HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[1], s));
-    HIP_TRY(hipMemcpyAsync(h->host, W.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h->host + 8, &W.result[1], sizeof(double), hipMemcpyDeviceToHost, s));
-    if (timing) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (timing) S.ms_setup = elapsed(ev[0], ev[1]);
-    if (h->host[kErrMatch]) return HWPM_EBADMATCH;
-    const int32_t n_long = h->host[kNumLong];
-    S.long_columns = n_long;
-    memcpy(&S.init_weight, h->host + 8, sizeof(double));
-
-    // 3. rounds
-    int32_t round = 0;
-    for (;;) {
-        if (opt.max_rounds > 0 && round >= opt.max_rounds) {
-            S.hit_round_cap = 1;
-            break;
-        }
-        const int slot = round % kSlots;
-        if (timing) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(launch_search(A, W, tile, kLongThreshold, slot, n_long > 0, s, h->cus));
-        if (timing) HIP_TRY(hipEventRecord(ev[3], s));
-        HIP_TRY(launch_resolve(W, slot, s, h->cus));
-        if (timing) HIP_TRY(hipEventRecord(ev[4], s));
-        HIP_TRY(launch_apply(A, W, slot, s, h->cus));
-        if (timing) HIP_TRY(hipEventRecord(ev[5], s));
-        HIP_TRY(hipMemcpyAsync(h->host, W.counters + kRoundBase + 2 * slot, 2 * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipStreamSynchronize(s));
-        const int32_t n_cand = h->host[0], n_applied = h->host[1];
-        if (round < HWPM_MAX_ROUND_STATS) {
-            S.round_candidates[round] = n_cand;
-            S.round_applied[round] = n_applied;
-        }
-        if (timing) {
-            const float ms = elapsed(ev[2], ev[3]);
-            S.ms_search += ms;
-            if (round == 0) S.ms_search_first = ms;
-            if (round < HWPM_MAX_ROUND_STATS) S.round_ms_search[round] = ms;
-            S.ms_resolve += elapsed(ev[3], ev[4]);
-            S.ms_apply += elapsed(ev[4], ev[5]);
-        }
-        S.cycles_applied += n_applied;
-        ++round;
-        // A round with candidates always flips at least one cycle (the
-        // candidate whose other column has the largest matched row).
-        if (n_cand > 0 && n_applied == 0) return HWPM_EINTERNAL;
-        if (n_applied == 0) break;
+int hwpm_match(hwpm_handle h, const hwpm_csc* Ain, int32_t* perm_out, double* total_out,
+               const hwpm_options* opt_in, hwpm_stats* stats, void* workspace,
+               size_t workspace_bytes) {
+    const auto t_begin = std::chrono::steady_clock::now();
+    if (!h) return HWPM_EINVAL;
+    int st = check_csc_args(Ain);
+    if (st != HWPM_OK) return st;
+    hwpm_options opt;
+    hwpm_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    st = check_options(opt);
+    if (st != HWPM_OK) return st;
+    const int32_t n = Ain->n;
+    if (n > 0 && !perm_out) return HWPM_EINVAL;
+    const size_t need = workspace_layout(n, Ain->nnz, nullptr, nullptr);
+    if (n > 0 && !workspace) return HWPM_EINVAL;
+    if (n > 0 && workspace_bytes < need) return HWPM_ENOMEM;
+    hwpm_stats S;
+    memset(&S, 0, sizeof(S));
+    if (n == 0) {
+        if (total_out) *total_out = 0.0;
+        if (stats) *stats = S;
+        return HWPM_OK;
     }
-    S.rounds = round;
-
-    // 4. outputs
-    if (timing) HIP_TRY(hipEventRecord(ev[6], s));
-    HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[0], s));
-    HIP_TRY(hipMemcpyAsync(perm_out, W.mc, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    HIP_TRY(hipMemcpyAsync(h->host + 8, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
-    if (timing) HIP_TRY(hipEventRecord(ev[7], s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (timing) S.ms_final = elapsed(ev[6], ev[7]);
-    double total;
-    memcpy(&total, h->host + 8, sizeof(double));
-    S.final_weight = total;
+    DeviceGuard g(h->device);
+    if (!g.ok) return HWPM_EDEVICE;
+    const Csc A = to_csc(Ain);
+    Work W;
+    Mcm M;
+    workspace_layout(n, A.nnz, (char*)workspace, &W, &M);
+    const bool timing = opt.timing != 0;
+    if (opt.check_csc) {
+        st = timed_check(h, A, W, timing, &S);
+        if (st != HWPM_OK) return st;
+    }
+    st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, timing, &S);
+    if (st != HWPM_OK) return st;
+    double total = 0.0;
+    st = run_improve(h, A, W, M.mc, perm_out, &total, opt, &S);
+    if (st != HWPM_OK) return st;
     if (total_out) *total_out = total;
     S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
     if (stats) *stats = S;

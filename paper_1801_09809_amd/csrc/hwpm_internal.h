@@ -17,9 +17,19 @@ enum CounterWord : int {
     kErrMatch = 1,     // matching validation flags
     kNumLong = 2,      // number of long columns
     kNumChunks = 3,    // chunks of the long-column search
-    kRoundBase = 8,    // [kRoundBase + 2*slot] = candidates, [+1] = applied
+    kRoundBase = 8,    // per-round words, kSlotWords per slot of the ring
     kCounterWords = 64,
 };
+
+// Per-round words of one ring slot.
+enum SlotWord : int {
+    kCand = 0,         // roots with a Step-C winner
+    kApplied = 1,      // cycles flipped
+    kRoots = 2,        // roots to search in this round (incremental mode)
+    kSlotWords = 4,
+};
+
+__host__ __device__ inline int slot_word(int slot, int w) { return kRoundBase + kSlotWords * slot + w; }
 
 // Matrix in CSC form (device pointers).
 struct Csc {
@@ -56,9 +66,63 @@ struct Work {
     int32_t* counters;  // kCounterWords
     double* result;     // [0] = total, [1] = initial weight
     int64_t max_chunks;
+    // pattern transpose (row lists) and per-entry mate columns, for the
+    // transposed probe
+    int64_t* rowptr;    // n + 1: row lists laid out by the column matched to
+                        // each row when the call starts (slot order)
+    int64_t* rstart;    // n: start of the row list of the row matched to column j
+    int32_t* rlen;      // n: its length
+    int32_t* colidx;    // nnz: columns of each row (any order within a row)
+    int64_t* cscpos;    // nnz: CSC position of each row-list entry
+    int32_t* mrk;       // nnz: m_i of the row of CSC entry k
+    int32_t* rowcnt;    // n: row counts, then fill cursors
+    int64_t* scan_sums; // block sums of the row-count scan
+    int32_t* flips;     // 4 per flipped cycle: (i, new mate j), (l, new mate c)
+    int32_t* dirty;     // n: root must be searched again (incremental mode)
+    int32_t* dirty_list;// n: the roots to search next round
+    // staging of the bucketed transpose
+    int32_t* colof;     // nnz: column of each CSC entry
+    int32_t* tp_row;
+    int32_t* tp_col;
+    int64_t* tp_pos;
+    int32_t* tp_cnt;    // bucket-major (bucket, segment) counts
+    int64_t* tp_off;    // their exclusive scan (+ total)
+    int64_t* tp_sums;
 };
 
-size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out);
+// Counter words of the matching phase.
+enum McmWord : int {
+    kMcmProposals = 0,
+    kMcmListLen = 1,
+    kMcmFrontier = 2,
+    kMcmNext = 3,
+    kMcmLevelLen = 4,
+    kMcmAugmented = 5,
+    kMcmWords = 16,
+};
+
+// Device arrays of the initial-matching phase (greedy + multi-source BFS).
+struct Mcm {
+    int32_t* mc;        // column -> row (-1: unmatched)
+    int32_t* mr;        // row -> column (-1: unmatched)
+    int32_t* prop_row;  // greedy: row proposed to
+    double* prop_w;     // greedy: its weight
+    unsigned long long* rkey;  // greedy: max proposal key per row
+    int32_t* racc;      // greedy: accepted proposer per row
+    int32_t* list;      // greedy: proposing columns
+    int32_t* tree_row;  // BFS: tree (root column) of each visited row, -1
+    int32_t* tree_col;  // BFS: tree of each frontier column
+    int32_t* parent;    // BFS: parent column of each visited row
+    int32_t* end_row;   // BFS: chosen endpoint per tree (root column)
+    unsigned long long* pkey;  // BFS: max parent key per row
+    int32_t* touched;   // BFS: row listed in the current level
+    int32_t* front_a;   // BFS: frontier buffers
+    int32_t* front_b;
+    int32_t* level;     // BFS: rows of the current level
+    int32_t* counters;  // kMcmWords
+};
+
+size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm = nullptr);
 
 // Launch wrappers (all asynchronous on `s`; return the launch status).
 hipError_t launch_check_csc(const Csc& A, const Work& W, hipStream_t s, int cus);
@@ -66,9 +130,23 @@ hipError_t launch_init_match(const Csc& A, const Work& W, const int32_t* mate_in
                              int32_t long_threshold, hipStream_t s);
 hipError_t launch_long_chunks(const Work& W, const Csc& A, hipStream_t s);
 hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t long_threshold,
-                         int slot, bool has_long, hipStream_t s, int cus);
+                         int slot, bool has_long, int probe, const int32_t* roots, int32_t nroots,
+                         bool incremental, hipStream_t s, int cus);
+hipError_t launch_collect(const Csc& A, const Work& W, int slot, hipStream_t s, int cus);
+hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
+                            hipStream_t s, int cus);
+hipError_t launch_mrk_update(const Work& W, int slot, bool incremental, hipStream_t s, int cus);
 hipError_t launch_resolve(const Work& W, int slot, hipStream_t s, int cus);
-hipError_t launch_apply(const Csc& A, const Work& W, int slot, hipStream_t s, int cus);
+hipError_t launch_apply(const Csc& A, const Work& W, int slot, bool transposed, hipStream_t s,
+                        int cus);
 hipError_t launch_tree_sum(const double* x, int64_t m, const Work& W, double* out, hipStream_t s);
+hipError_t launch_mcm_init(const Csc& A, const Mcm& M, const Work& W, int32_t long_threshold,
+                           hipStream_t s, int cus);
+hipError_t launch_greedy_round(const Csc& A, const Mcm& M, const Work& W, int heavy,
+                               int32_t long_threshold, bool has_long, hipStream_t s, int cus);
+hipError_t launch_bfs_roots(const Csc& A, const Mcm& M, hipStream_t s, int cus);
+hipError_t launch_bfs_level(const Csc& A, const Mcm& M, const int32_t* fr, int32_t nf,
+                            int32_t* next, int heavy, hipStream_t s, int cus);
+hipError_t launch_bfs_augment(const Csc& A, const Mcm& M, hipStream_t s, int cus);
 
 }  // namespace hwpm

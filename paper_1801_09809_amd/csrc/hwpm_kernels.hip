@@ -62,9 +62,9 @@ __device__ __forceinline__ bool better(double g1, int32_t i1, double g2, int32_t
     return g1 > g2 || (g1 == g2 && i1 < i2);
 }
 
-// Record the Step-C winner of root j (or its absence) and start Step D:
-// raise the max-gain slot of the other column c.
+// Record the Step-C winner of root j (or its absence).
 __device__ __forceinline__ void publish(const Work& W, int32_t j, const Cand& b, int slot) {
+    (void)slot;
     if (b.i == INT32_MAX) {
         W.best_i[j] = -1;
         return;
@@ -74,11 +74,6 @@ __device__ __forceinline__ void publish(const Work& W, int32_t j, const Cand& b,
     W.best_c[j] = b.c;
     W.best_k[j] = b.k;
     W.best_p[j] = b.p;
-    const unsigned long long gb = gain_bits(b.g);
-    if (__hip_atomic_load(&W.dgain[b.c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gb)
-        atomicMax(&W.dgain[b.c], gb);
-    const int32_t q = atomicAdd(&W.counters[kRoundBase + 2 * slot], 1);
-    W.cand[q] = j;
 }
 
 // One entry {i, j} of root column j (mate row mj, matched weight wmj):
@@ -274,7 +269,7 @@ __global__ __launch_bounds__(256) void k_search_short(Csc A, Work W, int32_t lon
 
 // Long columns: each block takes kLongChunk entries of one column and writes
 // a partial winner; k_merge_long reduces the partials of each column.
-__global__ __launch_bounds__(256) void k_search_long(Csc A, Work W) {
+__global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dirty) {
     __shared__ double sg[4];
     __shared__ int32_t si[4], sc[4];
     __shared__ int64_t sk[4], sp[4];
@@ -289,6 +284,7 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W) {
             if (W.chunk_off[m] <= cid) a = m; else z = m;
         }
         const int32_t j = W.long_list[a];
+        if (only_dirty && W.dirty[j] == 0) continue;  // block-uniform: result kept
         const int64_t c0 = A.col_ptr[j];
         const int64_t lo = c0 + (int64_t)(cid - W.chunk_off[a]) * kLongChunk;
         const int64_t hi0 = A.col_ptr[j + 1];
@@ -315,9 +311,13 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W) {
     }
 }
 
-__global__ void k_merge_long(Work W, int slot) {
+__global__ void k_merge_long(Work W, int slot, int only_dirty) {
     const int32_t nl = W.counters[kNumLong];
     for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nl; q += gridDim.x * blockDim.x) {
+        if (only_dirty) {
+            if (W.dirty[W.long_list[q]] == 0) continue;
+            W.dirty[W.long_list[q]] = 0;
+        }
         Cand b{0.0, INT32_MAX, -1, -1, -1};
         for (int64_t cid = W.chunk_off[q]; cid < W.chunk_off[q + 1]; ++cid) {
             if (better(W.part_g[cid], W.part_i[cid], b.g, b.i)) {
@@ -329,34 +329,35 @@ __global__ void k_merge_long(Work W, int slot) {
     }
 }
 
-hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t long_threshold,
-                         int slot, bool has_long, hipStream_t s, int cus) {
-    const int64_t threads = (int64_t)A.n * tile_width;
-    const unsigned blocks = (unsigned)((threads + 255) / 256);
-    switch (tile_width) {
-        case 4: hipLaunchKernelGGL(k_search_short<4>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot); break;
-        case 8: hipLaunchKernelGGL(k_search_short<8>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot); break;
-        case 16: hipLaunchKernelGGL(k_search_short<16>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot); break;
-        case 32: hipLaunchKernelGGL(k_search_short<32>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot); break;
-        case 64: hipLaunchKernelGGL(k_search_short<64>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot); break;
-        default: return hipErrorInvalidValue;
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || !has_long) return e;
-    hipLaunchKernelGGL(k_search_long, dim3(cus * 8), dim3(256), 0, s, A, W);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_long, dim3(64), dim3(256), 0, s, W, slot);
-    return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // Step D.  Pass 1 (the atomicMax of the gain bits) ran in publish(); pass 2
 // picks the smallest root among the roots that reached the maximum.  A column
 // that kept a cycle of its own accepts nothing.
 
+// The candidate list of the round (every root that holds a Step-C winner,
+// searched this round or kept from an earlier one) and pass 1 of Step D:
+// raise the max-gain slot of each candidate's other column.
+__global__ void k_collect(Csc A, Work W, int slot) {
+    for (int64_t jj = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; jj < A.n;
+         jj += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t j = (int32_t)jj;
+        if (W.best_i[j] < 0) continue;
+        const int32_t c = W.best_c[j];
+        const unsigned long long gb = gain_bits(W.best_g[j]);
+        if (__hip_atomic_load(&W.dgain[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gb)
+            atomicMax(&W.dgain[c], gb);
+        const int32_t q = atomicAdd(&W.counters[slot_word(slot, kCand)], 1);
+        W.cand[q] = j;
+    }
+}
+
+hipError_t launch_collect(const Csc& A, const Work& W, int slot, hipStream_t s, int cus) {
+    hipLaunchKernelGGL(k_collect, dim3(cus * 4), dim3(256), 0, s, A, W, slot);
+    return hipGetLastError();
+}
+
 __global__ void k_resolve(Work W, int slot) {
-    const int32_t nc = W.counters[kRoundBase + 2 * slot];
+    const int32_t nc = W.counters[slot_word(slot, kCand)];
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += gridDim.x * blockDim.x) {
         const int32_t j = W.cand[t];
         const int32_t c = W.best_c[j];
@@ -376,14 +377,10 @@ hipError_t launch_resolve(const Work& W, int slot, hipStream_t s, int cus) {
 // a root clears its own column (nobody reads it: its column accepts nothing),
 // the winner at column c clears c (the losers at c only compare the slot with
 // their own index, which neither the old nor the cleared value equals).
-__global__ void k_apply(Csc A, Work W, int slot) {
-    const int32_t nc = W.counters[kRoundBase + 2 * slot];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const int next = (slot + 1) % kSlots;
-        W.counters[kRoundBase + 2 * next] = 0;
-        W.counters[kRoundBase + 2 * next + 1] = 0;
-    }
-    int applied = 0;
+__global__ void k_apply(Csc A, Work W, int slot, int transposed) {
+    const int32_t nc = W.counters[slot_word(slot, kCand)];
+    if (blockIdx.x == 0 && threadIdx.x < kSlotWords)
+        W.counters[slot_word((slot + 1) % kSlots, threadIdx.x)] = 0;
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += gridDim.x * blockDim.x) {
         const int32_t j = W.cand[t];
         const int32_t c = W.best_c[j];
@@ -401,13 +398,620 @@ __global__ void k_apply(Csc A, Work W, int slot) {
         W.wm[c] = A.w[W.best_p[j]];
         W.dgain[c] = 0ull;
         __hip_atomic_store(&W.droot[c], kNoRoot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        ++applied;
+        if (transposed) {
+            // the row lists follow their rows: j now holds row i (was c's)
+            const int64_t sj = W.rstart[j], sc = W.rstart[c];
+            const int32_t lj = W.rlen[j], lc = W.rlen[c];
+            W.rstart[j] = sc; W.rlen[j] = lc;
+            W.rstart[c] = sj; W.rlen[c] = lj;
+        }
+        // the two rows whose mate changed, for the per-entry mate columns
+        const int32_t q = atomicAdd(&W.counters[slot_word(slot, kApplied)], 1);
+        W.flips[4 * (int64_t)q + 0] = i;
+        W.flips[4 * (int64_t)q + 1] = j;
+        W.flips[4 * (int64_t)q + 2] = l;
+        W.flips[4 * (int64_t)q + 3] = c;
     }
-    if (applied) atomicAdd(&W.counters[kRoundBase + 2 * slot + 1], applied);
 }
 
-hipError_t launch_apply(const Csc& A, const Work& W, int slot, hipStream_t s, int cus) {
-    hipLaunchKernelGGL(k_apply, dim3(cus * 2), dim3(256), 0, s, A, W, slot);
+hipError_t launch_apply(const Csc& A, const Work& W, int slot, bool transposed, hipStream_t s,
+                        int cus) {
+    hipLaunchKernelGGL(k_apply, dim3(cus * 2), dim3(256), 0, s, A, W, slot, transposed ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Pattern transpose, built once per solve: the row list of every row (the
+// columns holding an entry in that row, in no particular order) with the CSC
+// position of each entry.  Counting sort: per-row counts with atomics, an
+// exclusive scan, then a scatter through per-row atomic cursors.
+
+__global__ void k_row_count(Csc A, const int32_t* __restrict__ mr, int32_t* __restrict__ cnt) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < A.nnz;
+         k += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&cnt[mr[A.row_idx[k]]], 1);
+}
+
+// Exclusive scan of m int32 values into int64 out[0..m] (out[m] = total):
+// per-block scans of 2048 values, one block scanning the block sums, and an
+// add of the block offsets.
+__global__ __launch_bounds__(256) void k_scan_local(const int32_t* __restrict__ in, int64_t m,
+                                                    int64_t* __restrict__ out,
+                                                    int64_t* __restrict__ sums) {
+    __shared__ int64_t wsum[4];
+    const int64_t base = (int64_t)blockIdx.x * 2048 + threadIdx.x * 8;
+    int64_t v[8];
+    int64_t s = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const int64_t x = (base + e < m) ? in[base + e] : 0;
+        v[e] = s;
+        s += x;
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int64_t incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int64_t woff = 0;
+    for (int u = 0; u < wave; ++u) woff += wsum[u];
+    const int64_t excl = incl - s + woff;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+        if (base + e < m) out[base + e] = v[e] + excl;
+    if (threadIdx.x == 255) sums[blockIdx.x] = woff + incl;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_sums(int64_t* __restrict__ sums, int64_t nb,
+                                                    int64_t* __restrict__ total) {
+    __shared__ int64_t wsum[16];
+    __shared__ int64_t carry;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int64_t c0 = 0; c0 < nb; c0 += 1024) {
+        const int64_t idx = c0 + t;
+        const int64_t x = (idx < nb) ? sums[idx] : 0;
+        int64_t incl = x;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+        }
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        int64_t woff = carry;
+        for (int u = 0; u < wave; ++u) woff += wsum[u];
+        const int64_t excl = incl - x + woff;
+        if (idx < nb) sums[idx] = excl;
+        __syncthreads();
+        if (t == 1023) carry = excl + x;
+        __syncthreads();
+    }
+    if (t == 0) *total = carry;
+}
+
+__global__ void k_scan_add(int64_t* __restrict__ out, int64_t m, const int64_t* __restrict__ sums) {
+    for (int64_t x = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; x < m;
+         x += (int64_t)gridDim.x * blockDim.x)
+        out[x] += sums[x / 2048];
+}
+
+__device__ __forceinline__ void fill_entry(const Csc& A, const Work& W, int32_t j, int64_t k) {
+    const int32_t r = W.mr[A.row_idx[k]];   // slot: the column matched to the row
+    const int32_t slot = atomicAdd(&W.rowcnt[r], 1);
+    const int64_t e = W.rowptr[r] + slot;
+    W.colidx[e] = j;
+    W.cscpos[e] = k;
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_row_fill_short(Csc A, Work W, int32_t long_threshold) {
+    const int lane = threadIdx.x & (T - 1);
+    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
+    if (tile >= A.n) return;
+    const int32_t j = (int32_t)tile;
+    const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+    if (hi - lo > long_threshold) return;
+    for (int64_t k = lo + lane; k < hi; k += T) fill_entry(A, W, j, k);
+}
+
+__global__ __launch_bounds__(256) void k_row_fill_long(Csc A, Work W) {
+    const int32_t nl = W.counters[kNumLong];
+    const int32_t total = W.counters[kNumChunks];
+    for (int32_t cid = blockIdx.x; cid < total; cid += gridDim.x) {
+        int32_t a = 0, z = nl;
+        while (z - a > 1) {
+            const int32_t m = (a + z) >> 1;
+            if (W.chunk_off[m] <= cid) a = m; else z = m;
+        }
+        const int32_t j = W.long_list[a];
+        const int64_t lo = A.col_ptr[j] + (int64_t)(cid - W.chunk_off[a]) * kLongChunk;
+        const int64_t hi0 = A.col_ptr[j + 1];
+        const int64_t hi = (lo + kLongChunk < hi0) ? lo + kLongChunk : hi0;
+        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) fill_entry(A, W, j, k);
+    }
+}
+
+// Slot pointers of the row lists: rstart/rlen of column j locate the list of
+// the row matched to j.
+__global__ void k_slot_ptrs(Csc A, Work W) {
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < A.n;
+         j += (int64_t)gridDim.x * blockDim.x) {
+        W.rstart[j] = W.rowptr[j];
+        W.rlen[j] = (int32_t)(W.rowptr[j + 1] - W.rowptr[j]);
+    }
+}
+
+__global__ void k_mrk_fill(Csc A, Work W) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < A.nnz;
+         k += (int64_t)gridDim.x * blockDim.x)
+        W.mrk[k] = W.mr[A.row_idx[k]];
+}
+
+// Bucketed transpose (no global atomics): rows are grouped into buckets of
+// 2^rb consecutive rows.  Pass 1 counts, per segment of kTpSeg consecutive
+// entries and per bucket, the entries (LDS histogram); a scan turns the
+// bucket-major count table into offsets; a second sweep over the same
+// segments scatters (row, column, position) triples into their bucket and
+// fills the per-entry mate columns.  Pass 2 gives each bucket one block, which
+// counts its rows in LDS, writes their row pointers and places every entry.
+// The column of an entry comes from colof[], written once per call.
+constexpr int kTpSeg = 16384;     // entries per pass-1 segment
+constexpr int kTpMaxBuckets = 4096;
+constexpr int kTpMaxRows = 8192;  // rows per bucket (LDS counters)
+
+struct TpPlan {
+    int rb;          // log2 rows per bucket
+    int64_t nb;      // buckets
+    int64_t nseg;    // entry segments
+    bool ok;         // false: sizes beyond the LDS limits
+};
+
+TpPlan tp_plan(int64_t n, int64_t nnz) {
+    // about 1024 buckets; more (up to kTpMaxBuckets) once a bucket would
+    // exceed kTpMaxRows rows
+    TpPlan P;
+    int lg = 0;
+    while (((int64_t)1 << lg) < n) ++lg;
+    P.rb = lg - 10;
+    if (P.rb < 6) P.rb = 6;
+    while (P.rb > 6 && ((int64_t)1 << P.rb) > kTpMaxRows) --P.rb;
+    P.nb = (n + ((int64_t)1 << P.rb) - 1) >> P.rb;
+    P.nseg = (nnz + kTpSeg - 1) / kTpSeg;
+    if (P.nseg < 1) P.nseg = 1;
+    P.ok = P.nb <= kTpMaxBuckets && ((int64_t)1 << P.rb) <= kTpMaxRows && nnz < ((int64_t)1 << 31);
+    return P;
+}
+
+// colof[k] = column of entry k: a tile per short column, a block per chunk of
+// a long column.
+template <int T>
+__global__ __launch_bounds__(256) void k_colof_short(Csc A, Work W, int32_t long_threshold) {
+    const int lane = threadIdx.x & (T - 1);
+    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
+    if (tile >= A.n) return;
+    const int64_t lo = A.col_ptr[tile], hi = A.col_ptr[tile + 1];
+    if (hi - lo > long_threshold) return;
+    for (int64_t k = lo + lane; k < hi; k += T) W.colof[k] = (int32_t)tile;
+}
+
+__global__ __launch_bounds__(256) void k_colof_long(Csc A, Work W) {
+    const int32_t nl = W.counters[kNumLong];
+    const int32_t total = W.counters[kNumChunks];
+    for (int32_t cid = blockIdx.x; cid < total; cid += gridDim.x) {
+        int32_t a = 0, z = nl;
+        while (z - a > 1) {
+            const int32_t m = (a + z) >> 1;
+            if (W.chunk_off[m] <= cid) a = m; else z = m;
+        }
+        const int32_t j = W.long_list[a];
+        const int64_t lo = A.col_ptr[j] + (int64_t)(cid - W.chunk_off[a]) * kLongChunk;
+        const int64_t hi0 = A.col_ptr[j + 1];
+        const int64_t hi = (lo + kLongChunk < hi0) ? lo + kLongChunk : hi0;
+        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) W.colof[k] = j;
+    }
+}
+
+// Pass 1a: per-(bucket, segment) counts, written bucket-major.
+__global__ __launch_bounds__(1024) void k_tp_hist(Csc A, const int32_t* __restrict__ mr, int rb,
+                                                  int32_t nb, int32_t nseg, int32_t* __restrict__ cnt) {
+    __shared__ int32_t hist[kTpMaxBuckets];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
+    __syncthreads();
+    const int32_t seg = blockIdx.x;
+    const int64_t k0 = (int64_t)seg * kTpSeg;
+    const int64_t k1 = (k0 + kTpSeg < A.nnz) ? k0 + kTpSeg : A.nnz;
+#pragma unroll 4
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x)
+        atomicAdd(&hist[mr[A.row_idx[k]] >> rb], 1);
+    __syncthreads();
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[(int64_t)b * nseg + seg] = hist[b];
+}
+
+// Pass 1b: scatter (row, column, CSC position) into the buckets, and fill the
+// per-entry mate columns mrk[k] = m_(row of k).
+__global__ __launch_bounds__(1024) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
+                                                     const int64_t* __restrict__ off) {
+    __shared__ int32_t cur[kTpMaxBuckets];
+    __shared__ int64_t base[kTpMaxBuckets];
+    const int32_t seg = blockIdx.x;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        cur[b] = 0;
+        base[b] = off[(int64_t)b * nseg + seg];
+    }
+    __syncthreads();
+    const int64_t k0 = (int64_t)seg * kTpSeg;
+    const int64_t k1 = (k0 + kTpSeg < A.nnz) ? k0 + kTpSeg : A.nnz;
+#pragma unroll 4
+    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
+        const int32_t slot = W.mr[A.row_idx[k]];
+        const int32_t c = W.colof[k];
+        W.mrk[k] = slot;
+        const int32_t b = slot >> rb;
+        const int64_t pos = base[b] + atomicAdd(&cur[b], 1);
+        W.tp_row[pos] = slot;
+        W.tp_col[pos] = c;
+        W.tp_pos[pos] = k;
+    }
+}
+
+// Pass 2: one block per bucket.
+__global__ __launch_bounds__(1024) void k_tp_rows(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
+                                                  const int64_t* __restrict__ off) {
+    __shared__ int32_t rc[kTpMaxRows];
+    __shared__ int32_t wsum[16];
+    const int32_t b = blockIdx.x;
+    const int64_t r0 = (int64_t)b << rb;
+    const int64_t r1 = (r0 + ((int64_t)1 << rb) < A.n) ? r0 + ((int64_t)1 << rb) : A.n;
+    const int32_t nr = (int32_t)(r1 - r0);
+    const int64_t e0 = off[(int64_t)b * nseg];
+    const int64_t e1 = (b + 1 < nb) ? off[(int64_t)(b + 1) * nseg] : A.nnz;
+    if (b == nb - 1 && threadIdx.x == 0) W.rowptr[A.n] = A.nnz;
+    for (int x = threadIdx.x; x < nr; x += blockDim.x) rc[x] = 0;
+    __syncthreads();
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&rc[W.tp_row[e] - r0], 1);
+    __syncthreads();
+    // exclusive scan of rc[0..nr) in place: each thread owns a contiguous run
+    const int per = (nr + 1023) / 1024;
+    const int xb = threadIdx.x * per;
+    const int xe = (xb + per < nr) ? xb + per : nr;
+    int32_t run = 0;
+    for (int x = xb; x < xe; ++x) run += rc[x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int32_t acc = incl - run;
+    for (int u = 0; u < wave; ++u) acc += wsum[u];
+    __syncthreads();
+    for (int x = xb; x < xe; ++x) {
+        const int32_t v = rc[x];
+        rc[x] = acc;
+        W.rowptr[r0 + x] = e0 + acc;
+        W.rstart[r0 + x] = e0 + acc;
+        W.rlen[r0 + x] = v;
+        acc += v;
+    }
+    __syncthreads();
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+        const int64_t q = e0 + atomicAdd(&rc[W.tp_row[e] - r0], 1);
+        W.colidx[q] = W.tp_col[e];
+        W.cscpos[q] = W.tp_pos[e];
+    }
+}
+
+hipError_t launch_transpose_buckets(const Csc& A, const Work& W, int32_t long_threshold,
+                                    bool has_long, hipStream_t s, int cus) {
+    const TpPlan P = tp_plan(A.n, A.nnz);
+    const int32_t nb = (int32_t)P.nb, nseg = (int32_t)P.nseg;
+    const int64_t m = P.nb * P.nseg;
+    const unsigned tiles = (unsigned)(((int64_t)A.n * 16 + 255) / 256);
+    hipLaunchKernelGGL(k_colof_short<16>, dim3(tiles), dim3(256), 0, s, A, W, long_threshold);
+    if (has_long) hipLaunchKernelGGL(k_colof_long, dim3(cus * 8), dim3(256), 0, s, A, W);
+    hipLaunchKernelGGL(k_tp_hist, dim3(nseg), dim3(1024), 0, s, A, W.mr, P.rb, nb, nseg, W.tp_cnt);
+    const int64_t sb = (m + 2047) / 2048;
+    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)sb), dim3(256), 0, s, W.tp_cnt, m, W.tp_off, W.tp_sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, W.tp_sums, sb, W.tp_off + m);
+    hipLaunchKernelGGL(k_scan_add, dim3(cus * 8), dim3(256), 0, s, W.tp_off, m, W.tp_sums);
+    hipLaunchKernelGGL(k_tp_scatter, dim3(nseg), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+    hipLaunchKernelGGL(k_tp_rows, dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
+                            hipStream_t s, int cus) {
+    const int64_t n = A.n;
+    hipError_t e;
+    if (tp_plan(A.n, A.nnz).ok) {
+        // also fills mrk
+        return launch_transpose_buckets(A, W, long_threshold, has_long, s, cus);
+    } else {
+        // very large matrices: counting sort with global atomics
+        if ((e = hipMemsetAsync(W.rowcnt, 0, (size_t)n * sizeof(int32_t), s)) != hipSuccess) return e;
+        if (A.nnz > 0) hipLaunchKernelGGL(k_row_count, dim3(cus * 8), dim3(256), 0, s, A, W.mr, W.rowcnt);
+        const int64_t nb = (n + 2047) / 2048;
+        hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nb), dim3(256), 0, s, W.rowcnt, n, W.rowptr,
+                           W.scan_sums);
+        hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, W.scan_sums, nb, W.rowptr + n);
+        hipLaunchKernelGGL(k_scan_add, dim3(cus * 8), dim3(256), 0, s, W.rowptr, n, W.scan_sums);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(W.rowcnt, 0, (size_t)n * sizeof(int32_t), s)) != hipSuccess) return e;
+        const unsigned blocks = (unsigned)((n * 16 + 255) / 256);
+        hipLaunchKernelGGL(k_row_fill_short<16>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold);
+        if (has_long) hipLaunchKernelGGL(k_row_fill_long, dim3(cus * 8), dim3(256), 0, s, A, W);
+        hipLaunchKernelGGL(k_slot_ptrs, dim3(cus * 8), dim3(256), 0, s, A, W);
+    }
+    if (A.nnz > 0) hipLaunchKernelGGL(k_mrk_fill, dim3(cus * 8), dim3(256), 0, s, A, W);
+    return hipGetLastError();
+}
+
+// After the flips of a round: the entries of every row whose mate changed get
+// the new mate column (one block per flipped row).  In incremental mode the
+// columns of those entries are marked for the next round: a root's Step-C
+// result can change only if its own mate changed or one of its rows got a new
+// mate (every value its gains read is otherwise the same), and the flipped
+// columns themselves appear in the lists of their new rows.
+__global__ __launch_bounds__(256) void k_mrk_update(Work W, int slot, int incremental) {
+    const int64_t nf = 2 * (int64_t)W.counters[slot_word(slot, kApplied)];
+    const int next = (slot + 1) % kSlots;
+    for (int64_t f = blockIdx.x; f < nf; f += gridDim.x) {
+        const int32_t m = W.flips[2 * f + 1];   // new mate column of the flipped row
+        const int64_t b = W.rstart[m], e = b + W.rlen[m];
+        for (int64_t x = b + threadIdx.x; x < e; x += blockDim.x) {
+            W.mrk[W.cscpos[x]] = m;
+            if (incremental) {
+                const int32_t c = W.colidx[x];
+                if (__hip_atomic_load(&W.dirty[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+                    atomicExch(&W.dirty[c], 1) == 0) {
+                    const int32_t q = atomicAdd(&W.counters[slot_word(next, kRoots)], 1);
+                    W.dirty_list[q] = c;
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_mrk_update(const Work& W, int slot, bool incremental, hipStream_t s, int cus) {
+    hipLaunchKernelGGL(k_mrk_update, dim3(cus * 4), dim3(256), 0, s, W, slot, incremental ? 1 : 0);
+    return hipGetLastError();
+}
+
+// Steps A-C with the transposed probe, the GPU form of the marking trick of
+// the sequential algorithm (Section 4): for root j the row list of m_j is
+// read once per tile (contiguous) and every probe m_i of the tile is tested
+// against it with T cross-lane rotations; the per-entry mate columns m_i are
+// streamed from mrk (no gather).  Rows longer than kRowRotate fall back to the
+// binary-search probe of column m_i.  Both give the same (hit, position).
+constexpr int kRowRotate = 64;
+
+template <int T>
+__global__ __launch_bounds__(256) void k_search_rows(Csc A, Work W, int32_t long_threshold,
+                                                     int slot) {
+    const int lane = threadIdx.x & (T - 1);
+    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
+    if (tile >= A.n) return;  // tile-uniform
+    const int32_t j = (int32_t)tile;
+    const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+    if (hi - lo > long_threshold) return;
+    const int32_t mj = W.mc[j];
+    const double wmj = W.wm[j];
+    const int64_t rs = W.rstart[j];
+    const int32_t rlen = W.rlen[j];
+    Cand b{0.0, INT32_MAX, -1, -1, -1};
+    if (rlen <= kRowRotate) {
+        // row list of m_j, T entries per lane-chunk; -1 never equals a column
+        int32_t cv0 = (lane < rlen) ? W.colidx[rs + lane] : -1;
+        for (int64_t kc = lo; kc < hi; kc += T) {
+            const int64_t k = kc + lane;
+            int32_t i = -1, mi = -1;
+            if (k < hi) {
+                i = A.row_idx[k];
+                if (i > mj) mi = W.mrk[k];
+            }
+            int32_t q = -1;
+            for (int32_t rc = 0; rc < rlen; rc += T) {
+                const int32_t cv = (rc == 0) ? cv0
+                                             : ((rc + lane < rlen) ? W.colidx[rs + rc + lane] : -1);
+#pragma unroll
+                for (int sft = 0; sft < T; ++sft) {
+                    const int src = (lane + sft) & (T - 1);
+                    const int32_t v = __shfl(cv, src, T);
+                    if (mi >= 0 && v == mi) q = rc + src;
+                }
+            }
+            if (q >= 0) {
+                const int64_t p = W.cscpos[rs + q];
+                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
+                if (g > 0.0 && better(g, i, b.g, b.i)) {
+                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+                }
+            }
+        }
+    } else {
+        for (int64_t k = lo + lane; k < hi; k += T) {
+            const int32_t i = A.row_idx[k];
+            if (i <= mj) continue;
+            const int32_t mi = W.mrk[k];
+            const int64_t p = find_row(A.col_ptr, A.row_idx, mi, mj);
+            if (p < 0) continue;
+            const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
+            if (g > 0.0 && better(g, i, b.g, b.i)) {
+                b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+            }
+        }
+    }
+    reduce_best<T>(b);
+    if (lane == 0) publish(W, j, b, slot);
+}
+
+// Steps A-C, transposed probe, chunked form: a tile of T lanes per root, each
+// lane holding E entries of column j (i, m_i) and E entries of the row list
+// of m_j, so one root of up to T*E entries in both lists is searched with all
+// of its loads independent (one memory round trip per stage), and every probe
+// is compared with the whole row list through T cross-lane exchanges.  Roots
+// with a longer column or row list take the generic per-chunk path.
+template <int T, int E>
+__device__ __forceinline__ void root_generic(const Csc& A, const Work& W, int lane, int32_t j,
+                                             int64_t lo, int64_t hi, int32_t mj, double wmj,
+                                             int64_t rs, int32_t rlen, Cand& b) {
+    if (rlen <= kRowRotate) {
+        for (int64_t kc = lo; kc < hi; kc += T) {
+            const int64_t k = kc + lane;
+            int32_t i = -1, mi = -1;
+            if (k < hi) {
+                i = A.row_idx[k];
+                if (i > mj) mi = W.mrk[k];
+            }
+            int32_t q = -1;
+            for (int32_t rc = 0; rc < rlen; rc += T) {
+                const int32_t cv = (rc + lane < rlen) ? W.colidx[rs + rc + lane] : -1;
+#pragma unroll
+                for (int sft = 0; sft < T; ++sft) {
+                    const int32_t v = __shfl_xor(cv, sft, T);
+                    if (mi >= 0 && v == mi) q = rc + (lane ^ sft);
+                }
+            }
+            if (q >= 0) {
+                const int64_t p = W.cscpos[rs + q];
+                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
+                if (g > 0.0 && better(g, i, b.g, b.i)) {
+                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+                }
+            }
+        }
+    } else {
+        for (int64_t k = lo + lane; k < hi; k += T) {
+            const int32_t i = A.row_idx[k];
+            if (i <= mj) continue;
+            const int32_t mi = W.mrk[k];
+            const int64_t p = find_row(A.col_ptr, A.row_idx, mi, mj);
+            if (p < 0) continue;
+            const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
+            if (g > 0.0 && better(g, i, b.g, b.i)) {
+                b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+            }
+        }
+    }
+}
+
+template <int T, int E>
+__global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t long_threshold,
+                                                      int slot, const int32_t* __restrict__ roots,
+                                                      int32_t nroots) {
+    const int lane = threadIdx.x & (T - 1);
+    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
+    int32_t j;
+    if (roots) {
+        if (tile >= nroots) return;  // tile-uniform
+        j = roots[tile];
+    } else {
+        if (tile >= A.n) return;
+        j = (int32_t)tile;
+    }
+    const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+    const int64_t len = hi - lo;
+    if (len > long_threshold) return;  // split kernel handles it
+    if (roots && lane == 0) W.dirty[j] = 0;
+    Cand b{0.0, INT32_MAX, -1, -1, -1};
+    if (len > 1) {  // a single entry is the matched one: no cycle
+        const int32_t mj = W.mc[j];
+        const double wmj = W.wm[j];
+        const int64_t rs = W.rstart[j];
+        const int32_t rlen = W.rlen[j];
+        if (len <= T * E && rlen <= T * E) {
+            int32_t iv[E], mv[E], rv[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t k = lo + lane + T * e;
+                iv[e] = (k < hi) ? A.row_idx[k] : -1;
+                const int32_t x = lane + T * e;
+                rv[e] = (x < rlen) ? W.colidx[rs + x] : -1;
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t k = lo + lane + T * e;
+                mv[e] = (iv[e] > mj) ? W.mrk[k] : -1;
+            }
+            int32_t qv[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) qv[e] = -1;
+#pragma unroll
+            for (int sft = 0; sft < T; ++sft) {
+#pragma unroll
+                for (int f = 0; f < E; ++f) {
+                    const int32_t v = __shfl_xor(rv[f], sft, T);
+                    const int32_t x = (lane ^ sft) + T * f;
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+                        if (mv[e] >= 0 && v == mv[e]) qv[e] = x;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (qv[e] >= 0) {
+                    const int64_t k = lo + lane + T * e;
+                    const int64_t p = W.cscpos[rs + qv[e]];
+                    const double g = (A.w[k] + A.w[p]) - (W.wm[mv[e]] + wmj);
+                    if (g > 0.0 && better(g, iv[e], b.g, b.i)) {
+                        b.g = g; b.i = iv[e]; b.c = mv[e]; b.k = k; b.p = p;
+                    }
+                }
+            }
+        } else {
+            root_generic<T, E>(A, W, lane, j, lo, hi, mj, wmj, rs, rlen, b);
+        }
+    }
+    reduce_best<T>(b);
+    if (lane == 0) publish(W, j, b, slot);
+}
+
+hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t long_threshold,
+                         int slot, bool has_long, int probe, const int32_t* roots, int32_t nroots,
+                         bool incremental, hipStream_t s, int cus) {
+    const int64_t threads = (int64_t)(roots ? nroots : A.n) * tile_width;
+    const unsigned blocks = (unsigned)((threads + 255) / 256);
+    const bool transposed = probe == 2;
+#define HWPM_SEARCH(TW)                                                                     \
+    if (transposed)                                                                         \
+        hipLaunchKernelGGL(k_search_rows<TW>, dim3(blocks), dim3(256), 0, s, A, W,          \
+                           long_threshold, slot);                                           \
+    else                                                                                    \
+        hipLaunchKernelGGL(k_search_short<TW>, dim3(blocks), dim3(256), 0, s, A, W,         \
+                           long_threshold, slot);
+    if (probe == 3) {
+        switch (tile_width) {
+            case 4: hipLaunchKernelGGL((k_search_chunk<4, 8>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, nroots); break;
+            case 8: hipLaunchKernelGGL((k_search_chunk<8, 4>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, nroots); break;
+            case 16: hipLaunchKernelGGL((k_search_chunk<16, 2>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, nroots); break;
+            case 32: hipLaunchKernelGGL((k_search_chunk<32, 1>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, nroots); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else switch (tile_width) {
+        case 4: HWPM_SEARCH(4) break;
+        case 8: HWPM_SEARCH(8) break;
+        case 16: HWPM_SEARCH(16) break;
+        case 32: HWPM_SEARCH(32) break;
+        case 64: HWPM_SEARCH(64) break;
+        default: return hipErrorInvalidValue;
+    }
+#undef HWPM_SEARCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !has_long) return e;
+    const int only_dirty = (roots && incremental) ? 1 : 0;
+    hipLaunchKernelGGL(k_search_long, dim3(cus * 8), dim3(256), 0, s, A, W, only_dirty);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_merge_long, dim3(64), dim3(256), 0, s, W, slot, only_dirty);
     return hipGetLastError();
 }
 
@@ -476,7 +1080,7 @@ hipError_t launch_tree_sum(const double* x, int64_t m, const Work& W, double* ou
 
 static inline size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out) {
+size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm) {
     const size_t N = (size_t)(n > 0 ? n : 0);
     const size_t Z = (size_t)(nnz > 0 ? nnz : 0);
     const size_t max_chunks = Z / kLongChunk + N + 1;
@@ -512,6 +1116,46 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out) {
     W.counters = (int32_t*)take(kCounterWords * 4);
     W.result = (double*)take(4 * 8);
     W.max_chunks = (int64_t)max_chunks;
+    W.rowptr = (int64_t*)take((N + 1) * 8);
+    W.rstart = (int64_t*)take(N * 8);
+    W.rlen = (int32_t*)take(N * 4);
+    W.colidx = (int32_t*)take(Z * 4);
+    W.cscpos = (int64_t*)take(Z * 8);
+    W.mrk = (int32_t*)take(Z * 4);
+    W.rowcnt = (int32_t*)take(N * 4);
+    W.scan_sums = (int64_t*)take((N / 2048 + 2) * 8);
+    W.flips = (int32_t*)take(N * 4 * 4 / 2 + 16);
+    W.dirty = (int32_t*)take(N * 4);
+    W.dirty_list = (int32_t*)take(N * 4);
+    const TpPlan P = tp_plan(n, nnz);
+    const size_t tpm = P.ok ? (size_t)(P.nb * P.nseg) : 0;
+    const size_t tpz = P.ok ? Z : 0;
+    W.colof = (int32_t*)take(tpz * 4);
+    W.tp_row = (int32_t*)take(tpz * 4);
+    W.tp_col = (int32_t*)take(tpz * 4);
+    W.tp_pos = (int64_t*)take(tpz * 8);
+    W.tp_cnt = (int32_t*)take(tpm * 4);
+    W.tp_off = (int64_t*)take((tpm + 1) * 8);
+    W.tp_sums = (int64_t*)take((tpm / 2048 + 2) * 8);
+    Mcm M;
+    M.mc = (int32_t*)take(N * 4);
+    M.mr = (int32_t*)take(N * 4);
+    M.prop_row = (int32_t*)take(N * 4);
+    M.prop_w = (double*)take(N * 8);
+    M.rkey = (unsigned long long*)take(N * 8);
+    M.racc = (int32_t*)take(N * 4);
+    M.list = (int32_t*)take(N * 4);
+    M.tree_row = (int32_t*)take(N * 4);
+    M.tree_col = (int32_t*)take(N * 4);
+    M.parent = (int32_t*)take(N * 4);
+    M.end_row = (int32_t*)take(N * 4);
+    M.pkey = (unsigned long long*)take(N * 8);
+    M.touched = (int32_t*)take(N * 4);
+    M.front_a = (int32_t*)take(N * 4);
+    M.front_b = (int32_t*)take(N * 4);
+    M.level = (int32_t*)take(N * 4);
+    M.counters = (int32_t*)take(kMcmWords * 4);
+    if (mcm) *mcm = M;
     if (out) *out = W;
     return off;
 }

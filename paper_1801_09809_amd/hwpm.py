@@ -30,7 +30,7 @@ MAX_ROUND_STATS = 512
 
 EXPORTED = (
     "hwpm_default_options", "hwpm_strerror", "hwpm_create", "hwpm_destroy",
-    "hwpm_workspace_bytes", "hwpm_check_csc", "hwpm_improve",
+    "hwpm_workspace_bytes", "hwpm_check_csc", "hwpm_improve", "hwpm_match",
 )
 
 
@@ -56,6 +56,9 @@ class hwpm_options(ctypes.Structure):
         ("check_csc", ctypes.c_int32),
         ("timing", ctypes.c_int32),
         ("tile_width", ctypes.c_int32),
+        ("probe", ctypes.c_int32),
+        ("mcm_plain", ctypes.c_int32),
+        ("full_search", ctypes.c_int32),
     ]
 
 
@@ -65,29 +68,39 @@ class hwpm_stats(ctypes.Structure):
         ("hit_round_cap", ctypes.c_int32),
         ("cycles_applied", ctypes.c_int64),
         ("long_columns", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("greedy_rounds", ctypes.c_int32),
+        ("greedy_cardinality", ctypes.c_int32),
+        ("mcm_cardinality", ctypes.c_int32),
+        ("mcm_phases", ctypes.c_int32),
+        ("mcm_levels", ctypes.c_int32),
         ("init_weight", ctypes.c_double),
         ("final_weight", ctypes.c_double),
         ("ms_check", ctypes.c_float),
+        ("ms_greedy", ctypes.c_float),
+        ("ms_mcm", ctypes.c_float),
         ("ms_setup", ctypes.c_float),
+        ("ms_transpose", ctypes.c_float),
         ("ms_search", ctypes.c_float),
         ("ms_resolve", ctypes.c_float),
         ("ms_apply", ctypes.c_float),
         ("ms_final", ctypes.c_float),
         ("ms_total", ctypes.c_float),
         ("ms_search_first", ctypes.c_float),
+        ("ms_reserved", ctypes.c_float),
         ("round_candidates", ctypes.c_int32 * MAX_ROUND_STATS),
         ("round_applied", ctypes.c_int32 * MAX_ROUND_STATS),
         ("round_ms_search", ctypes.c_float * MAX_ROUND_STATS),
+        ("round_roots", ctypes.c_int32 * MAX_ROUND_STATS),
     ]
 
     def as_dict(self) -> dict:
         nr = min(self.rounds, MAX_ROUND_STATS)
         d = {name: getattr(self, name) for name, _ in self._fields_
-             if not name.startswith("round_") and name != "reserved"}
+             if not name.startswith("round_") and name != "ms_reserved"}
         d["round_candidates"] = list(self.round_candidates[:nr])
         d["round_applied"] = list(self.round_applied[:nr])
         d["round_ms_search"] = list(self.round_ms_search[:nr])
+        d["round_roots"] = list(self.round_roots[:nr])
         return d
 
 
@@ -114,6 +127,10 @@ def load_library(path: str = LIB_PATH):
         lib.hwpm_workspace_bytes.argtypes = [i32, i64, ctypes.POINTER(ctypes.c_size_t)]
         lib.hwpm_check_csc.restype = ctypes.c_int
         lib.hwpm_check_csc.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, ctypes.c_size_t]
+        lib.hwpm_match.restype = ctypes.c_int
+        lib.hwpm_match.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(hwpm_options), ctypes.POINTER(hwpm_stats), vp,
+                                   ctypes.c_size_t]
         lib.hwpm_improve.restype = ctypes.c_int
         lib.hwpm_improve.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, vp,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(hwpm_options),
@@ -184,6 +201,21 @@ def hwpm_improve(handle: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: i
     return st, total.value, stats
 
 
+def hwpm_match(handle: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: int, weight_ptr: int,
+               perm_out_ptr: int, ws_ptr: int, ws_bytes: int, options: hwpm_options | None = None,
+               want_stats: bool = True):
+    """Returns (status, total, stats or None)."""
+    A = _csc(n, nnz, col_ptr_ptr, row_idx_ptr, weight_ptr)
+    total = ctypes.c_double(0.0)
+    stats = hwpm_stats() if want_stats else None
+    st = load_library().hwpm_match(
+        ctypes.c_void_p(handle), ctypes.byref(A), ctypes.c_void_p(perm_out_ptr), ctypes.byref(total),
+        ctypes.byref(options) if options is not None else None,
+        ctypes.byref(stats) if stats is not None else None,
+        ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes))
+    return st, total.value, stats
+
+
 # ---------------------------------------------------------------------------
 # convenience wrapper over torch tensors
 
@@ -237,9 +269,41 @@ class Solver:
             return hwpm_check_csc(self.handle, n, nnz, col_ptr.data_ptr(), row_idx.data_ptr(),
                                   w.data_ptr(), ws.data_ptr(), ws.numel())
 
+    @staticmethod
+    def options(max_rounds=0, check_csc=True, timing=False, tile_width=0, probe=0,
+                mcm_plain=False, full_search=False) -> hwpm_options:
+        opt = hwpm_default_options()
+        opt.max_rounds = int(max_rounds)
+        opt.check_csc = int(bool(check_csc))
+        opt.timing = int(bool(timing))
+        opt.tile_width = int(tile_width)
+        opt.probe = int(probe)
+        opt.mcm_plain = int(bool(mcm_plain))
+        opt.full_search = int(bool(full_search))
+        return opt
+
+    def match(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
+              perm_out: torch.Tensor | None = None, **kw) -> ImproveResult:
+        n = col_ptr.numel() - 1
+        nnz = row_idx.numel()
+        self._check(col_ptr, torch.int64, "col_ptr")
+        self._check(row_idx, torch.int32, "row_idx")
+        self._check(w, torch.float64, "w", nnz)
+        if perm_out is None:
+            perm_out = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._check(perm_out, torch.int32, "perm_out", n)
+        ws = self._workspace(n, nnz)
+        st, total, stats = hwpm_match(self.handle, n, nnz, col_ptr.data_ptr(), row_idx.data_ptr(),
+                                      w.data_ptr(), perm_out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                      self.options(**kw))
+        if st != HWPM_OK:
+            raise HwpmError(st, "hwpm_match")
+        return ImproveResult(perm_out, total, stats.as_dict())
+
     def improve(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
                 mate_in: torch.Tensor, perm_out: torch.Tensor | None = None, max_rounds: int = 0,
-                check_csc: bool = True, timing: bool = False, tile_width: int = 0) -> ImproveResult:
+                check_csc: bool = True, timing: bool = False, tile_width: int = 0,
+                probe: int = 0, full_search: bool = False) -> ImproveResult:
         n = col_ptr.numel() - 1
         nnz = row_idx.numel()
         self._check(col_ptr, torch.int64, "col_ptr")
@@ -250,11 +314,7 @@ class Solver:
             perm_out = torch.empty(n, dtype=torch.int32, device=self.device)
         self._check(perm_out, torch.int32, "perm_out", n)
         ws = self._workspace(n, nnz)
-        opt = hwpm_default_options()
-        opt.max_rounds = int(max_rounds)
-        opt.check_csc = int(bool(check_csc))
-        opt.timing = int(bool(timing))
-        opt.tile_width = int(tile_width)
+        opt = self.options(max_rounds, check_csc, timing, tile_width, probe, False, full_search)
         st, total, stats = hwpm_improve(self.handle, n, nnz, col_ptr.data_ptr(), row_idx.data_ptr(),
                                         w.data_ptr(), mate_in.data_ptr(), perm_out.data_ptr(),
                                         ws.data_ptr(), ws.numel(), opt)

@@ -41,16 +41,17 @@ def test_status_codes_match_header():
 def test_struct_layouts():
     # the ctypes mirrors must match the C layout (offsets of the last fields)
     assert ctypes.sizeof(hwpm.hwpm_csc) == 40
-    assert ctypes.sizeof(hwpm.hwpm_options) == 16
+    assert ctypes.sizeof(hwpm.hwpm_options) == 28
     s = hwpm.hwpm_stats
-    assert s.init_weight.offset == 24 and s.ms_check.offset == 40
-    assert s.round_candidates.offset == 72
-    assert ctypes.sizeof(s) == 72 + 3 * 4 * hwpm.MAX_ROUND_STATS
+    assert s.init_weight.offset == 40 and s.ms_check.offset == 56
+    assert s.round_candidates.offset == 104
+    assert ctypes.sizeof(s) == 104 + 4 * 4 * hwpm.MAX_ROUND_STATS
 
 
 def test_default_options():
     o = hwpm.hwpm_default_options()
-    assert (o.max_rounds, o.check_csc, o.timing, o.tile_width) == (0, 1, 0, 0)
+    assert (o.max_rounds, o.check_csc, o.timing, o.tile_width, o.probe, o.mcm_plain,
+            o.full_search) == (0, 1, 0, 0, 0, 0, 0)
 
 
 def test_workspace_bytes():
@@ -58,7 +59,8 @@ def test_workspace_bytes():
     b1 = hwpm.hwpm_workspace_bytes(1000, 9000)
     b2 = hwpm.hwpm_workspace_bytes(1 << 20, 17_825_657)
     assert 0 < b0 < b1 < b2
-    assert b2 < 200 * (1 << 20) * 4  # ~ O(100 B per column)
+    # O(nnz + n): row lists, their staging and per-entry mates; per-vertex state
+    assert b2 < 60 * 17_825_657 + 400 * (1 << 20)
     with pytest.raises(hwpm.HwpmError) as e:
         hwpm.hwpm_workspace_bytes(-1, 0)
     assert e.value.status == hwpm.HWPM_EINVAL

@@ -93,48 +93,65 @@ def test_golden_on_gpu(solver, case):
 # ---------------------------------------------------------------------------
 # small and medium random cases, all tile widths
 
+# search configurations: column binary search; transposed row lists; chunked
+# transposed (incremental rounds, the default); chunked with full rounds
+PROBES = ["p1", "p2", "p3", "p3full"]
+_PROBE_KW = {"p1": dict(probe=1), "p2": dict(probe=2), "p3": dict(probe=3),
+             "p3full": dict(probe=3, full_search=True)}
+
+
+@pytest.mark.parametrize("probe", PROBES)
 @pytest.mark.parametrize("n,d,seed,intw", [
     (1, 1, 0, False), (2, 2, 1, True), (3, 3, 2, True), (5, 2, 3, False), (8, 8, 4, True),
     (63, 3, 5, False), (64, 4, 6, True), (65, 5, 7, False), (257, 9, 8, True),
     (1000, 2, 9, False), (4099, 6, 10, True), (20011, 8, 11, False), (20011, 8, 12, True),
+    (3001, 70, 13, True),  # rows longer than the rotation limit
 ])
-def test_random_vs_oracle(solver, n, d, seed, intw):
+def test_random_vs_oracle(solver, n, d, seed, intw, probe):
     wl = small_random(n, d, seed, integer_weights=intw, weight_range=2)
-    run_both(solver, wl)
+    run_both(solver, wl, **_PROBE_KW[probe])
 
 
+@pytest.mark.parametrize("probe", PROBES)
 @pytest.mark.parametrize("tile", [4, 8, 16, 32, 64])
-def test_tile_widths_identical(solver, tile):
+def test_tile_widths_identical(solver, tile, probe):
+    if probe.startswith("p3") and tile == 64:
+        pytest.skip("the chunked kernel takes tiles of 4 to 32 lanes")
     wl = workload(0)
-    run_both(solver, wl, tile_width=tile)
+    run_both(solver, wl, tile_width=tile, **_PROBE_KW[probe])
     wl2 = small_random(5003, 30, 77, integer_weights=True, weight_range=1)  # heavy ties
-    run_both(solver, wl2, tile_width=tile)
+    run_both(solver, wl2, tile_width=tile, **_PROBE_KW[probe])
 
 
-def test_stencil_small(solver):
+@pytest.mark.parametrize("probe", PROBES)
+def test_stencil_small(solver, probe):
     wl = stencil27(23, 17, 11, 2101, 3101, name="stencil_23x17x11")
-    run_both(solver, wl)
+    run_both(solver, wl, **_PROBE_KW[probe])
 
 
-def test_stencil_integer_ties(solver):
+@pytest.mark.parametrize("probe", PROBES)
+def test_stencil_integer_ties(solver, probe):
     wl = stencil27(16, 16, 16, 2102, 3102, name="stencil_16cubed_int")
     rng = np.random.default_rng(5)
     wl.w = rng.integers(-2, 3, size=wl.nnz).astype(np.float64)
-    run_both(solver, wl)
+    run_both(solver, wl, **_PROBE_KW[probe])
 
 
+@pytest.mark.parametrize("probe", PROBES)
 @pytest.mark.parametrize("scale", [12, 14])
-def test_rmat_long_columns(solver, scale):
+def test_rmat_long_columns(solver, scale, probe):
     wl = rmat(scale, 16, 1000 + scale, 2000 + scale, 3000 + scale, name=f"rmat_scale{scale}")
     assert np.diff(wl.col_ptr).max() > 256  # exercises the split search
-    gpu, ref = run_both(solver, wl)
+    assert np.bincount(wl.row_idx).max() > 64  # and the long-row fallback
+    gpu, ref = run_both(solver, wl, **_PROBE_KW[probe])
     assert gpu[2]["long_columns"] > 0
 
 
-def test_round_cap(solver):
+@pytest.mark.parametrize("probe", PROBES)
+def test_round_cap(solver, probe):
     wl = stencil27(20, 20, 20, 2103, 3103, name="stencil_20cubed")
     for cap in (1, 2, 3):
-        run_both(solver, wl, max_rounds=cap)
+        run_both(solver, wl, max_rounds=cap, **_PROBE_KW[probe])
 
 
 def test_empty_matrix(solver):
@@ -160,9 +177,9 @@ def test_aliasing_and_determinism(solver):
     ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
     dev = solver.device
     cp, ri, w = _dev(wl.col_ptr, dev), _dev(wl.row_idx, dev), _dev(wl.w, dev)
-    for rep in range(3):
+    for rep in range(4):
         mate = _dev(wl.planted, dev)
-        res = solver.improve(cp, ri, w, mate, perm_out=mate)  # in place
+        res = solver.improve(cp, ri, w, mate, perm_out=mate, **_PROBE_KW[PROBES[rep]])  # in place
         assert np.array_equal(mate.cpu().numpy(), ref.perm)
         assert res.total == ref.total
 
@@ -258,36 +275,44 @@ def _no_positive_4cycle(wl, perm):
     return int((g > 0).sum()), wm
 
 
-def _full(solver, k, max_rounds=0):
+def _full(solver, k, max_rounds=0, probe="p3"):
     wl = workload(k)
     dev = solver.device
     cp, ri, w = _dev(wl.col_ptr, dev), _dev(wl.row_idx, dev), _dev(wl.w, dev)
     from paper_1801_09809_amd import hwpm
     assert solver.check_csc(cp, ri, w) == hwpm.HWPM_OK
-    print(f"[gpu] workload {k} ({wl.name}) max_rounds={max_rounds}", flush=True)
-    res = solver.improve(cp, ri, w, _dev(wl.planted, dev), max_rounds=max_rounds, check_csc=False)
+    print(f"[gpu] workload {k} ({wl.name}) max_rounds={max_rounds} probe={probe}", flush=True)
+    res = solver.improve(cp, ri, w, _dev(wl.planted, dev), max_rounds=max_rounds, check_csc=False,
+                         **_PROBE_KW[probe])
     torch.cuda.synchronize()
     return wl, (res.perm.cpu().numpy(), res.total, res.stats)
 
 
 @pytest.mark.parametrize("k", [1, 2])
 def test_full_workload_bit_exact(solver, k):
-    wl, gpu = _full(solver, k)
+    wl, gpu = _full(solver, k, probe="p3full")  # the benchmark's configuration
     ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
     assert_same(wl, gpu, ref)
     bad, wm = _no_positive_4cycle(wl, gpu[0])
     assert bad == 0
     assert oracle_tree_sum(wm) == gpu[1]
+    for probe in PROBES:
+        _, other = _full(solver, k, probe=probe)
+        assert_same(wl, other, ref)
 
 
-def test_full_rmat_first_rounds_bit_exact(solver):
-    wl, gpu = _full(solver, 3, max_rounds=3)
+@pytest.mark.parametrize("probe", PROBES)
+def test_full_rmat_first_rounds_bit_exact(solver, probe):
+    wl, gpu = _full(solver, 3, max_rounds=3, probe=probe)
     ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted, 3)
     assert_same(wl, gpu, ref)
 
 
 def test_full_rmat_converged_properties(solver):
-    wl, (perm, total, st) = _full(solver, 3)
+    wl, (perm, total, st) = _full(solver, 3, probe="p3")  # default: incremental rounds
+    _, other = _full(solver, 3, probe="p3full")
+    assert np.array_equal(other[0], perm) and other[1] == total
+    assert other[2]["round_applied"] == st["round_applied"]
     assert st["hit_round_cap"] == 0 and st["rounds"] > 3
     assert np.array_equal(np.sort(perm), np.arange(wl.n))
     bad, wm = _no_positive_4cycle(wl, perm)
@@ -297,3 +322,76 @@ def test_full_rmat_converged_properties(solver):
     # every round with candidates flipped at least one cycle, the last none
     rc, ra = st["round_candidates"], st["round_applied"]
     assert all(a > 0 for c, a in zip(rc[:-1], ra[:-1])) and ra[-1] == 0 and rc[-1] == 0
+
+
+# ---------------------------------------------------------------------------
+# the whole pipeline (greedy + BFS matching + rounds) against the oracle
+
+def gpu_match(solver, wl, **kw):
+    print(f"[gpu] match {wl.name} n={wl.n} nnz={wl.nnz} {kw}", flush=True)
+    dev = solver.device
+    res = solver.match(_dev(wl.col_ptr, dev), _dev(wl.row_idx, dev), _dev(wl.w, dev), **kw)
+    torch.cuda.synchronize()
+    return res.perm.cpu().numpy(), res.total, res.stats
+
+
+def match_both(solver, wl, plain=False, **kw):
+    from oracle import oracle_greedy, oracle_match
+    ref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w, heavy=not plain,
+                       max_rounds=kw.get("max_rounds", 0))
+    gcard, _, _ = oracle_greedy(wl.n, wl.col_ptr, wl.row_idx, wl.w, heavy=not plain)
+    gpu = gpu_match(solver, wl, mcm_plain=plain, **kw)
+    assert_same(wl, gpu, ref)
+    st = gpu[2]
+    assert st["greedy_cardinality"] == gcard
+    assert st["mcm_cardinality"] == ref.mcm_cardinality == wl.n
+    return gpu, ref
+
+
+@pytest.mark.parametrize("plain", [False, True])
+@pytest.mark.parametrize("n,d,seed,intw", [
+    (1, 1, 0, False), (2, 1, 1, True), (7, 2, 2, True), (64, 1, 3, False), (65, 2, 4, True),
+    (1000, 1, 5, False), (3001, 3, 6, True), (20011, 2, 7, False), (20011, 6, 8, True),
+])
+def test_match_random_vs_oracle(solver, n, d, seed, intw, plain):
+    wl = small_random(n, d, seed, integer_weights=intw, weight_range=2)
+    match_both(solver, wl, plain=plain)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_match_stencil_and_rmat(solver, plain):
+    match_both(solver, stencil27(21, 13, 9, 2104, 3104, name="stencil_21x13x9"), plain=plain)
+    match_both(solver, rmat(13, 16, 1013, 2013, 3013, name="rmat_scale13"), plain=plain)
+
+
+def test_match_singular(solver):
+    from paper_1801_09809_amd import hwpm
+    from oracle import oracle_match
+    dev = solver.device
+    for n, holes, seed in ((50, 0.3, 1), (2000, 0.2, 2), (5000, 0.05, 3)):
+        wl = small_random(n, 1, seed)
+        rng = np.random.default_rng(seed)
+        keep = np.ones(wl.nnz, dtype=bool)
+        for j in range(n):  # drop planted entries so the matrix may be singular
+            if rng.random() < holes:
+                lo, hi = wl.col_ptr[j], wl.col_ptr[j + 1]
+                keep[lo + np.searchsorted(wl.row_idx[lo:hi], wl.planted[j])] = False
+        counts = np.array([keep[wl.col_ptr[j]:wl.col_ptr[j + 1]].sum() for j in range(n)])
+        cp = np.zeros(n + 1, dtype=np.int64); cp[1:] = np.cumsum(counts)
+        ri, w = wl.row_idx[keep], wl.w[keep]
+        ref = oracle_match(n, cp, ri, w)
+        perm = torch.full((n,), -7, dtype=torch.int32, device=dev)
+        if ref.status == -2:
+            with pytest.raises(hwpm.HwpmError) as e:
+                solver.match(_dev(cp, dev), _dev(ri, dev), _dev(w, dev), perm_out=perm)
+            assert e.value.status == hwpm.HWPM_ESINGULAR
+            assert (perm.cpu().numpy() == -7).all()  # outputs untouched
+        else:
+            res = solver.match(_dev(cp, dev), _dev(ri, dev), _dev(w, dev), perm_out=perm)
+            assert np.array_equal(perm.cpu().numpy(), ref.perm) and res.total == ref.total
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_match_full_workload(solver, k):
+    wl = workload(k)
+    match_both(solver, wl, check_csc=True)

@@ -28,14 +28,14 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 
 
-def search_bytes(nnz: int, n: int, candidates: float) -> float:
-    """Algorithmic bytes of one cycle-search launch over the whole matrix:
-    every row index once (4 B/entry); per column col_ptr (8 B), its mate row,
-    the mate column of one row and the matched weight (4 + 4 + 8 B), and the
-    written Step-C flag (4 B); per root that keeps a cycle the winner record
-    (gain 8, other column 4, two positions 16, the Step-D slot 8, the list
-    entry 4 = 40 B)."""
-    return 4.0 * nnz + 28.0 * n + 40.0 * candidates
+def search_bytes(nnz: int, n: int) -> float:
+    """Algorithmic bytes of one full cycle-search launch with the transposed
+    probe: each edge is visited twice per round (in its column for the pruned
+    half: row index 4 B + mate column 4 B; in the row list of m_j: 4 B), i.e.
+    8 B per entry, plus 16 B per column (column pointer, m_j, w(m_j, j)).  The
+    24 B per closing-edge hit are left out (a lower bound: hits are rare on
+    the random workload)."""
+    return 8.0 * nnz + 16.0 * n
 
 
 def load_traffic(kernel: str):
@@ -148,8 +148,7 @@ def main(argv=None) -> int:
     if not args.no_timing:
         ms_search = float(np.mean([s["ms_search"] for s in stats]))
         launch_ms = ms_search / rounds
-        cands = float(np.mean([np.mean(s["round_candidates"]) for s in stats]))
-        alg = search_bytes(wl.nnz, wl.n, cands)
+        alg = search_bytes(wl.nnz, wl.n)
         achieved = alg / (launch_ms / 1e3) / 1e9
         traffic = load_traffic("k_search_short")
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

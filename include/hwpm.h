@@ -94,7 +94,9 @@ typedef struct {
      * 0 = default; 1 = binary search of row m_j in column m_i; 2 = build the
      * pattern transpose once per call and test m_i against the row list of
      * m_j (the marking trick of Section 4), with per-entry mate columns kept
-     * up to date across flips. */
+     * up to date across flips, one entry per lane; 3 = the same with 8
+     * entries per lane in 4-lane tiles; 4 = the same with 16-byte vector
+     * loads (used when row_idx is 16-byte aligned, else 3). */
     int32_t probe;
     /* Initial matching of hwpm_match (Section 5.2): 0 = heavy-edge tie-break
      * in the greedy and BFS steps (the paper's heuristic, default);

@@ -88,15 +88,16 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     const bool timing = opt.timing != 0;
     hipEvent_t* ev = h->ev;
     const int tile = opt.tile_width ? opt.tile_width : kDefaultTile;
-    const int probe = opt.probe ? opt.probe : kDefaultProbe;
+    int probe = opt.probe ? opt.probe : kDefaultProbe;
+    // the vector kernel reads row_idx in aligned 16-byte windows
+    if (probe == 4 && ((uintptr_t)A.row_idx & 15)) probe = 3;
     const bool transposed = probe >= 2;
-    const bool incremental = probe == 3 && !opt.full_search;
+    const bool incremental = probe >= 3 && !opt.full_search;
     // 2. set-up: mates, matched weights, matching validation, long columns
     if (timing) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(hipMemsetAsync(W.counters, 0, kCounterWords * sizeof(int32_t), s));
     HIP_TRY(hipMemsetAsync(W.mr, 0xff, (size_t)n * sizeof(int32_t), s));
     HIP_TRY(launch_init_match(A, W, mate_in, kLongThreshold, s));
-    HIP_TRY(launch_long_chunks(W, A, s));
     HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[1], s));
     HIP_TRY(hipMemcpyAsync(h->host, W.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->host + 8, &W.result[1], sizeof(double), hipMemcpyDeviceToHost, s));
@@ -105,6 +106,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     if (timing) S.ms_setup = elapsed(ev[0], ev[1]);
     if (h->host[kErrMatch]) return HWPM_EBADMATCH;
     const int32_t n_long = h->host[kNumLong];
+    if (n_long > 0) HIP_TRY(launch_long_chunks(W, A, s));
     S.long_columns = n_long;
     memcpy(&S.init_weight, h->host + 8, sizeof(double));
     if (transposed) {
@@ -203,7 +205,7 @@ int check_options(const hwpm_options& opt) {
     const int tile = opt.tile_width ? opt.tile_width : kDefaultTile;
     if (tile != 4 && tile != 8 && tile != 16 && tile != 32 && tile != 64) return HWPM_EINVAL;
     const int probe = opt.probe ? opt.probe : kDefaultProbe;
-    if (probe < 1 || probe > 3) return HWPM_EINVAL;
+    if (probe < 1 || probe > 4) return HWPM_EINVAL;
     if (probe == 3 && tile == 64) return HWPM_EINVAL;
     if (opt.mcm_plain != 0 && opt.mcm_plain != 1) return HWPM_EINVAL;
     if (opt.full_search != 0 && opt.full_search != 1) return HWPM_EINVAL;

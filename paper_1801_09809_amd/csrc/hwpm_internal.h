@@ -55,6 +55,7 @@ struct Work {
     int32_t* cand;      // compacted list of roots with a Step-C winner
     int32_t* long_list; // columns searched by the split kernel
     int64_t* chunk_off; // chunk prefix per long column (n_long + 1)
+    int32_t* chunk_col; // long column (index into long_list) of every chunk
     double* part_g;     // per-chunk partial winners
     int32_t* part_i;
     int32_t* part_c;
@@ -84,10 +85,14 @@ struct Work {
     int32_t* colof;     // nnz: column of each CSC entry
     int32_t* tp_row;
     int32_t* tp_col;
-    int64_t* tp_pos;
+    int32_t* tp_pos;
     int32_t* tp_cnt;    // bucket-major (bucket, segment) counts
     int64_t* tp_off;    // their exclusive scan (+ total)
     int64_t* tp_sums;
+    int32_t* tp_row2;   // pass-2 output, grouped by sub-bucket
+    int32_t* tp_col2;
+    int32_t* tp_pos2;
+    int64_t* tp_sub;    // start of every sub-bucket (+ total)
 };
 
 // Counter words of the matching phase.

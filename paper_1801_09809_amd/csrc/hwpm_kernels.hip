@@ -182,9 +182,10 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
         const int32_t r = mate_in[j];
         if (r < 0 || r >= A.n) {
             atomicOr(&W.counters[kErrMatch], 1);
+            W.mc[j] = -1;
             continue;
         }
-        if (atomicCAS(&W.mr[r], -1, j) != -1) atomicOr(&W.counters[kErrMatch], 2);
+        W.mr[r] = j;  // a row claimed twice keeps one writer: k_check_match sees the other
         W.mc[j] = r;
         const int64_t p = find_row(A.col_ptr, A.row_idx, j, r);
         if (p < 0) {
@@ -196,20 +197,33 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
     }
 }
 
+// n columns mapped into n rows form a permutation iff every column reads
+// itself back through the row it claimed.
+__global__ void k_check_match(Csc A, Work W) {
+    for (int64_t jj = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; jj < A.n;
+         jj += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t r = W.mc[jj];
+        if (r >= 0 && W.mr[r] != (int32_t)jj) atomicOr(&W.counters[kErrMatch], 2);
+    }
+}
+
 hipError_t launch_init_match(const Csc& A, const Work& W, const int32_t* mate_in,
                              int32_t long_threshold, hipStream_t s) {
     const int64_t blocks = ((int64_t)A.n + 255) / 256;
-    hipLaunchKernelGGL(k_init_match, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256),
-                       0, s, A, W, mate_in, long_threshold);
+    const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
+    hipLaunchKernelGGL(k_init_match, dim3(g), dim3(256), 0, s, A, W, mate_in, long_threshold);
+    hipLaunchKernelGGL(k_check_match, dim3(g), dim3(256), 0, s, A, W);
     return hipGetLastError();
 }
 
 // Chunk table of the long columns: chunk_off[q] = number of kLongChunk-entry
-// chunks in long columns 0..q-1.  One block, sequential over 1024 segments.
+// chunks in long columns 0..q-1.  One block: each thread sums a contiguous
+// run of long columns, a block scan of the run sums, then each thread writes
+// its run's offsets.
 __global__ __launch_bounds__(1024) void k_long_chunks(Work W, Csc A) {
-    __shared__ int64_t seg[1024];
+    __shared__ int64_t wsum[16];
     const int32_t nl = W.counters[kNumLong];
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     const int64_t per = ((int64_t)nl + 1023) / 1024;
     const int64_t b = t * per, e = (b + per < nl) ? b + per : nl;
     int64_t sum = 0;
@@ -218,25 +232,27 @@ __global__ __launch_bounds__(1024) void k_long_chunks(Work W, Csc A) {
         const int64_t len = A.col_ptr[j + 1] - A.col_ptr[j];
         sum += (len + kLongChunk - 1) / kLongChunk;
     }
-    seg[t] = sum;
-    __syncthreads();
-    if (t == 0) {
-        int64_t run = 0;
-        for (int u = 0; u < 1024; ++u) {
-            const int64_t v = seg[u];
-            seg[u] = run;
-            run += v;
-        }
-        W.counters[kNumChunks] = (int32_t)run;
-        W.chunk_off[nl] = run;
+    int64_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
     }
+    if (lane == 63) wsum[wave] = incl;
     __syncthreads();
-    int64_t run = seg[t];
+    int64_t run = incl - sum;
+    for (int u = 0; u < wave; ++u) run += wsum[u];
+    if (t == 1023) {
+        W.counters[kNumChunks] = (int32_t)(run + sum);
+        W.chunk_off[nl] = run + sum;
+    }
     for (int64_t q = b; q < e; ++q) {
         W.chunk_off[q] = run;
         const int32_t j = W.long_list[q];
         const int64_t len = A.col_ptr[j + 1] - A.col_ptr[j];
-        run += (len + kLongChunk - 1) / kLongChunk;
+        const int64_t nc = (len + kLongChunk - 1) / kLongChunk;
+        for (int64_t c = 0; c < nc; ++c) W.chunk_col[run + c] = (int32_t)q;
+        run += nc;
     }
 }
 
@@ -276,13 +292,9 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
     const int32_t nl = W.counters[kNumLong];
     const int32_t total = W.counters[kNumChunks];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    (void)nl;
     for (int32_t cid = blockIdx.x; cid < total; cid += gridDim.x) {
-        // q = last long column whose first chunk is <= cid
-        int32_t a = 0, z = nl;  // chunk_off[a] <= cid < chunk_off[z]
-        while (z - a > 1) {
-            const int32_t m = (a + z) >> 1;
-            if (W.chunk_off[m] <= cid) a = m; else z = m;
-        }
+        const int32_t a = W.chunk_col[cid];  // long column of this chunk
         const int32_t j = W.long_list[a];
         if (only_dirty && W.dirty[j] == 0) continue;  // block-uniform: result kept
         const int64_t c0 = A.col_ptr[j];
@@ -521,14 +533,9 @@ __global__ __launch_bounds__(256) void k_row_fill_short(Csc A, Work W, int32_t l
 }
 
 __global__ __launch_bounds__(256) void k_row_fill_long(Csc A, Work W) {
-    const int32_t nl = W.counters[kNumLong];
     const int32_t total = W.counters[kNumChunks];
     for (int32_t cid = blockIdx.x; cid < total; cid += gridDim.x) {
-        int32_t a = 0, z = nl;
-        while (z - a > 1) {
-            const int32_t m = (a + z) >> 1;
-            if (W.chunk_off[m] <= cid) a = m; else z = m;
-        }
+        const int32_t a = W.chunk_col[cid];
         const int32_t j = W.long_list[a];
         const int64_t lo = A.col_ptr[j] + (int64_t)(cid - W.chunk_off[a]) * kLongChunk;
         const int64_t hi0 = A.col_ptr[j + 1];
@@ -553,36 +560,38 @@ __global__ void k_mrk_fill(Csc A, Work W) {
         W.mrk[k] = W.mr[A.row_idx[k]];
 }
 
-// Bucketed transpose (no global atomics): rows are grouped into buckets of
-// 2^rb consecutive rows.  Pass 1 counts, per segment of kTpSeg consecutive
-// entries and per bucket, the entries (LDS histogram); a scan turns the
-// bucket-major count table into offsets; a second sweep over the same
-// segments scatters (row, column, position) triples into their bucket and
-// fills the per-entry mate columns.  Pass 2 gives each bucket one block, which
-// counts its rows in LDS, writes their row pointers and places every entry.
-// The column of an entry comes from colof[], written once per call.
-constexpr int kTpSeg = 16384;     // entries per pass-1 segment
-constexpr int kTpMaxBuckets = 4096;
-constexpr int kTpMaxRows = 8192;  // rows per bucket (LDS counters)
+// Bucketed transpose (no global atomics), keyed by slot = the column matched
+// to an entry's row.  Slots are grouped into buckets of 2^rb consecutive
+// slots.  Pass 1 works on tiles of kTpTile consecutive entries: it counts each
+// tile's entries per bucket (LDS histogram); a scan of the bucket-major count
+// table gives every (bucket, tile) run its place; a second sweep sorts each
+// tile by bucket in LDS and writes the (slot, column, position) triples out in
+// contiguous runs, filling the per-entry mate columns on the way.  Pass 2
+// gives each bucket one block, which counts its slots in LDS, writes the slot
+// pointers and places every entry (the bucket's output range is small enough
+// to stay in L2).  The column of an entry comes from colof[].
+constexpr int kTpTile = 4096;     // entries per pass-1 tile (256 threads x 16)
+constexpr int kTpMaxBuckets = 1024;
+constexpr int kTpMaxRows = 8192;  // slots per bucket (LDS counters of pass 2)
 
 struct TpPlan {
-    int rb;          // log2 rows per bucket
+    int rb;          // log2 slots per bucket
     int64_t nb;      // buckets
-    int64_t nseg;    // entry segments
+    int64_t nseg;    // pass-1 tiles
     bool ok;         // false: sizes beyond the LDS limits
 };
 
 TpPlan tp_plan(int64_t n, int64_t nnz) {
-    // about 1024 buckets; more (up to kTpMaxBuckets) once a bucket would
-    // exceed kTpMaxRows rows
+    // about 512 buckets; more (up to kTpMaxBuckets) once a bucket would exceed
+    // kTpMaxRows slots
     TpPlan P;
     int lg = 0;
     while (((int64_t)1 << lg) < n) ++lg;
-    P.rb = lg - 10;
+    P.rb = lg - 9;
     if (P.rb < 6) P.rb = 6;
     while (P.rb > 6 && ((int64_t)1 << P.rb) > kTpMaxRows) --P.rb;
     P.nb = (n + ((int64_t)1 << P.rb) - 1) >> P.rb;
-    P.nseg = (nnz + kTpSeg - 1) / kTpSeg;
+    P.nseg = (nnz + kTpTile - 1) / kTpTile;
     if (P.nseg < 1) P.nseg = 1;
     P.ok = P.nb <= kTpMaxBuckets && ((int64_t)1 << P.rb) <= kTpMaxRows && nnz < ((int64_t)1 << 31);
     return P;
@@ -601,14 +610,9 @@ __global__ __launch_bounds__(256) void k_colof_short(Csc A, Work W, int32_t long
 }
 
 __global__ __launch_bounds__(256) void k_colof_long(Csc A, Work W) {
-    const int32_t nl = W.counters[kNumLong];
     const int32_t total = W.counters[kNumChunks];
     for (int32_t cid = blockIdx.x; cid < total; cid += gridDim.x) {
-        int32_t a = 0, z = nl;
-        while (z - a > 1) {
-            const int32_t m = (a + z) >> 1;
-            if (W.chunk_off[m] <= cid) a = m; else z = m;
-        }
+        const int32_t a = W.chunk_col[cid];
         const int32_t j = W.long_list[a];
         const int64_t lo = A.col_ptr[j] + (int64_t)(cid - W.chunk_off[a]) * kLongChunk;
         const int64_t hi0 = A.col_ptr[j + 1];
@@ -617,71 +621,59 @@ __global__ __launch_bounds__(256) void k_colof_long(Csc A, Work W) {
     }
 }
 
-// Pass 1a: per-(bucket, segment) counts, written bucket-major.
-__global__ __launch_bounds__(1024) void k_tp_hist(Csc A, const int32_t* __restrict__ mr, int rb,
-                                                  int32_t nb, int32_t nseg, int32_t* __restrict__ cnt) {
+// Pass 1a: per-(bucket, tile) counts, written bucket-major.  The slot of
+// every entry (mrk) is filled beforehand by k_mrk_fill.
+__global__ __launch_bounds__(256) void k_tp_hist(Csc A, const int32_t* __restrict__ mrk, int rb,
+                                                 int32_t nb, int32_t nseg, int32_t* __restrict__ cnt) {
     __shared__ int32_t hist[kTpMaxBuckets];
     for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int32_t seg = blockIdx.x;
-    const int64_t k0 = (int64_t)seg * kTpSeg;
-    const int64_t k1 = (k0 + kTpSeg < A.nnz) ? k0 + kTpSeg : A.nnz;
-#pragma unroll 4
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x)
-        atomicAdd(&hist[mr[A.row_idx[k]] >> rb], 1);
+    const int64_t k0 = (int64_t)seg * kTpTile;
+    int32_t sl[kTpTile / 256];
+#pragma unroll
+    for (int u = 0; u < kTpTile / 256; ++u) {
+        const int64_t k = k0 + threadIdx.x + 256 * u;
+        sl[u] = (k < A.nnz) ? mrk[k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kTpTile / 256; ++u)
+        if (sl[u] >= 0) atomicAdd(&hist[sl[u] >> rb], 1);
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[(int64_t)b * nseg + seg] = hist[b];
 }
 
-// Pass 1b: scatter (row, column, CSC position) into the buckets, and fill the
-// per-entry mate columns mrk[k] = m_(row of k).
-__global__ __launch_bounds__(1024) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
-                                                     const int64_t* __restrict__ off) {
-    __shared__ int32_t cur[kTpMaxBuckets];
-    __shared__ int64_t base[kTpMaxBuckets];
+// Pass 1b: sort the tile by bucket in LDS, write the triples in runs.
+__global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
+                                                    const int64_t* __restrict__ off) {
+    __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[kTpTile];
+    __shared__ int32_t hist[kTpMaxBuckets], start[kTpMaxBuckets], base[kTpMaxBuckets];
+    __shared__ int32_t wsum[4];
     const int32_t seg = blockIdx.x;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        cur[b] = 0;
-        base[b] = off[(int64_t)b * nseg + seg];
+        hist[b] = 0;
+        base[b] = (int32_t)off[(int64_t)b * nseg + seg];
     }
     __syncthreads();
-    const int64_t k0 = (int64_t)seg * kTpSeg;
-    const int64_t k1 = (k0 + kTpSeg < A.nnz) ? k0 + kTpSeg : A.nnz;
-#pragma unroll 4
-    for (int64_t k = k0 + threadIdx.x; k < k1; k += blockDim.x) {
-        const int32_t slot = W.mr[A.row_idx[k]];
-        const int32_t c = W.colof[k];
-        W.mrk[k] = slot;
-        const int32_t b = slot >> rb;
-        const int64_t pos = base[b] + atomicAdd(&cur[b], 1);
-        W.tp_row[pos] = slot;
-        W.tp_col[pos] = c;
-        W.tp_pos[pos] = k;
+    const int64_t k0 = (int64_t)seg * kTpTile;
+    constexpr int U = kTpTile / 256;
+    int32_t sl[U], co[U], rk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = k0 + threadIdx.x + 256 * u;
+        const bool ok = k < A.nnz;
+        sl[u] = ok ? W.mrk[k] : -1;
+        co[u] = ok ? W.colof[k] : -1;
     }
-}
-
-// Pass 2: one block per bucket.
-__global__ __launch_bounds__(1024) void k_tp_rows(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
-                                                  const int64_t* __restrict__ off) {
-    __shared__ int32_t rc[kTpMaxRows];
-    __shared__ int32_t wsum[16];
-    const int32_t b = blockIdx.x;
-    const int64_t r0 = (int64_t)b << rb;
-    const int64_t r1 = (r0 + ((int64_t)1 << rb) < A.n) ? r0 + ((int64_t)1 << rb) : A.n;
-    const int32_t nr = (int32_t)(r1 - r0);
-    const int64_t e0 = off[(int64_t)b * nseg];
-    const int64_t e1 = (b + 1 < nb) ? off[(int64_t)(b + 1) * nseg] : A.nnz;
-    if (b == nb - 1 && threadIdx.x == 0) W.rowptr[A.n] = A.nnz;
-    for (int x = threadIdx.x; x < nr; x += blockDim.x) rc[x] = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if (sl[u] >= 0) rk[u] = atomicAdd(&hist[sl[u] >> rb], 1);
     __syncthreads();
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&rc[W.tp_row[e] - r0], 1);
-    __syncthreads();
-    // exclusive scan of rc[0..nr) in place: each thread owns a contiguous run
-    const int per = (nr + 1023) / 1024;
-    const int xb = threadIdx.x * per;
-    const int xe = (xb + per < nr) ? xb + per : nr;
+    // exclusive scan of hist[0..nb): each thread owns up to 4 buckets
+    const int per = (nb + 255) / 256;
+    const int bb = threadIdx.x * per, be = (bb + per < nb) ? bb + per : nb;
     int32_t run = 0;
-    for (int x = xb; x < xe; ++x) run += rc[x];
+    for (int b = bb; b < be; ++b) run += hist[b];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t incl = run;
 #pragma unroll
@@ -693,20 +685,159 @@ __global__ __launch_bounds__(1024) void k_tp_rows(Csc A, Work W, int rb, int32_t
     __syncthreads();
     int32_t acc = incl - run;
     for (int u = 0; u < wave; ++u) acc += wsum[u];
-    __syncthreads();
-    for (int x = xb; x < xe; ++x) {
-        const int32_t v = rc[x];
-        rc[x] = acc;
-        W.rowptr[r0 + x] = e0 + acc;
-        W.rstart[r0 + x] = e0 + acc;
-        W.rlen[r0 + x] = v;
-        acc += v;
+    for (int b = bb; b < be; ++b) {
+        start[b] = acc;
+        acc += hist[b];
     }
     __syncthreads();
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
-        const int64_t q = e0 + atomicAdd(&rc[W.tp_row[e] - r0], 1);
-        W.colidx[q] = W.tp_col[e];
-        W.cscpos[q] = W.tp_pos[e];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (sl[u] >= 0) {
+            const int32_t x = start[sl[u] >> rb] + rk[u];
+            s_slot[x] = sl[u];
+            s_col[x] = co[u];
+            s_pos[x] = (int32_t)(k0 + threadIdx.x + 256 * u);
+        }
+    }
+    __syncthreads();
+    const int32_t len = (int32_t)((k0 + kTpTile < A.nnz) ? kTpTile : A.nnz - k0);
+    for (int32_t e = threadIdx.x; e < len; e += blockDim.x) {
+        const int32_t slot = s_slot[e];
+        const int32_t b = slot >> rb;
+        const int32_t g = base[b] + (e - start[b]);
+        W.tp_row[g] = slot;
+        W.tp_col[g] = s_col[e];
+        W.tp_pos[g] = s_pos[e];
+    }
+}
+
+// Pass 2: one block per bucket splits it into kTpSub sub-buckets of
+// 2^(rb - 6) consecutive slots, again sorting tiles in LDS so the triples
+// leave in runs, and records where each sub-bucket starts.
+constexpr int kTpSub = 64;
+
+__global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
+                                                   const int64_t* __restrict__ off) {
+    __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[kTpTile];
+    __shared__ int32_t hist[kTpSub], start[kTpSub], cursor[kTpSub];
+    const int32_t b = blockIdx.x;
+    const int64_t r0 = (int64_t)b << rb;
+    const int sb = rb - 6;
+    const int64_t e0 = off[(int64_t)b * nseg];
+    const int64_t e1 = (b + 1 < nb) ? off[(int64_t)(b + 1) * nseg] : A.nnz;
+    const int t = threadIdx.x;
+    if (t < kTpSub) hist[t] = 0;
+    __syncthreads();
+    for (int64_t e = e0 + t; e < e1; e += blockDim.x) atomicAdd(&hist[(W.tp_row[e] - r0) >> sb], 1);
+    __syncthreads();
+    if (t < 64) {  // one wave scans the 64 sub-bucket counts
+        const int32_t v = hist[t];
+        int32_t incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t x = __shfl_up(incl, o, 64);
+            if (t >= o) incl += x;
+        }
+        cursor[t] = incl - v;  // relative to e0
+        W.tp_sub[(int64_t)b * kTpSub + t] = e0 + incl - v;
+        if (b == nb - 1 && t == 63) W.tp_sub[(int64_t)nb * kTpSub] = A.nnz;
+    }
+    __syncthreads();
+    for (int64_t t0 = e0; t0 < e1; t0 += kTpTile) {
+        const int32_t len = (int32_t)((t0 + kTpTile < e1) ? kTpTile : e1 - t0);
+        if (t < kTpSub) hist[t] = 0;
+        __syncthreads();
+        int32_t sl[4], co[4], ps[4], rk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int32_t x = t + 1024 * u;
+            sl[u] = (x < len) ? W.tp_row[t0 + x] : -1;
+            co[u] = (x < len) ? W.tp_col[t0 + x] : 0;
+            ps[u] = (x < len) ? W.tp_pos[t0 + x] : 0;
+            if (sl[u] >= 0) rk[u] = atomicAdd(&hist[(sl[u] - r0) >> sb], 1);
+        }
+        __syncthreads();
+        if (t < 64) {
+            const int32_t v = hist[t];
+            int32_t incl = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t x = __shfl_up(incl, o, 64);
+                if (t >= o) incl += x;
+            }
+            start[t] = incl - v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (sl[u] >= 0) {
+                const int32_t x = start[(sl[u] - r0) >> sb] + rk[u];
+                s_slot[x] = sl[u];
+                s_col[x] = co[u];
+                s_pos[x] = ps[u];
+            }
+        }
+        __syncthreads();
+        for (int32_t x = t; x < len; x += blockDim.x) {
+            const int32_t g = (s_slot[x] - (int32_t)r0) >> sb;
+            const int64_t q = e0 + cursor[g] + (x - start[g]);
+            W.tp_row2[q] = s_slot[x];
+            W.tp_col2[q] = s_col[x];
+            W.tp_pos2[q] = s_pos[x];
+        }
+        __syncthreads();
+        if (t < kTpSub) cursor[t] += hist[t];
+        __syncthreads();
+    }
+}
+
+// Pass 3: one block per sub-bucket (at most 128 slots, a few hundred entries
+// on average): count its slots, write their pointers, place every entry.  The
+// block's output window is small, so the scattered placement stays in L2.
+__global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t nb) {
+    __shared__ int32_t rc[kTpMaxRows / kTpSub];
+    const int32_t g = blockIdx.x;
+    const int32_t b = g / kTpSub, sub = g % kTpSub;
+    const int sb = rb - 6;
+    const int64_t s0 = ((int64_t)b << rb) + ((int64_t)sub << sb);
+    const int64_t s1 = (s0 + ((int64_t)1 << sb) < A.n) ? s0 + ((int64_t)1 << sb) : A.n;
+    const int32_t nr = (s1 > s0) ? (int32_t)(s1 - s0) : 0;
+    const int64_t e0 = W.tp_sub[g], e1 = W.tp_sub[g + 1];
+    const int t = threadIdx.x;
+    for (int x = t; x < nr; x += blockDim.x) rc[x] = 0;
+    __syncthreads();
+    for (int64_t e = e0 + t; e < e1; e += blockDim.x) atomicAdd(&rc[W.tp_row2[e] - s0], 1);
+    __syncthreads();
+    if (t < 64) {  // one wave scans up to 128 slot counts, two per lane
+        const int32_t a0 = (2 * t < nr) ? rc[2 * t] : 0;
+        const int32_t a1 = (2 * t + 1 < nr) ? rc[2 * t + 1] : 0;
+        const int32_t v = a0 + a1;
+        int32_t incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t x = __shfl_up(incl, o, 64);
+            if (t >= o) incl += x;
+        }
+        const int32_t ex = incl - v;
+        if (2 * t < nr) {
+            rc[2 * t] = ex;
+            W.rowptr[s0 + 2 * t] = e0 + ex;
+            W.rstart[s0 + 2 * t] = e0 + ex;
+            W.rlen[s0 + 2 * t] = a0;
+        }
+        if (2 * t + 1 < nr) {
+            rc[2 * t + 1] = ex + a0;
+            W.rowptr[s0 + 2 * t + 1] = e0 + ex + a0;
+            W.rstart[s0 + 2 * t + 1] = e0 + ex + a0;
+            W.rlen[s0 + 2 * t + 1] = a1;
+        }
+    }
+    if (g == nb * kTpSub - 1 && t == 0) W.rowptr[A.n] = A.nnz;
+    __syncthreads();
+    for (int64_t e = e0 + t; e < e1; e += blockDim.x) {
+        const int64_t q = e0 + atomicAdd(&rc[W.tp_row2[e] - s0], 1);
+        W.colidx[q] = W.tp_col2[e];
+        W.cscpos[q] = W.tp_pos2[e];
     }
 }
 
@@ -718,13 +849,15 @@ hipError_t launch_transpose_buckets(const Csc& A, const Work& W, int32_t long_th
     const unsigned tiles = (unsigned)(((int64_t)A.n * 16 + 255) / 256);
     hipLaunchKernelGGL(k_colof_short<16>, dim3(tiles), dim3(256), 0, s, A, W, long_threshold);
     if (has_long) hipLaunchKernelGGL(k_colof_long, dim3(cus * 8), dim3(256), 0, s, A, W);
-    hipLaunchKernelGGL(k_tp_hist, dim3(nseg), dim3(1024), 0, s, A, W.mr, P.rb, nb, nseg, W.tp_cnt);
+    hipLaunchKernelGGL(k_mrk_fill, dim3(cus * 8), dim3(256), 0, s, A, W);
+    hipLaunchKernelGGL(k_tp_hist, dim3(nseg), dim3(256), 0, s, A, W.mrk, P.rb, nb, nseg, W.tp_cnt);
     const int64_t sb = (m + 2047) / 2048;
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)sb), dim3(256), 0, s, W.tp_cnt, m, W.tp_off, W.tp_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, W.tp_sums, sb, W.tp_off + m);
     hipLaunchKernelGGL(k_scan_add, dim3(cus * 8), dim3(256), 0, s, W.tp_off, m, W.tp_sums);
-    hipLaunchKernelGGL(k_tp_scatter, dim3(nseg), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-    hipLaunchKernelGGL(k_tp_rows, dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+    hipLaunchKernelGGL(k_tp_scatter, dim3(nseg), dim3(256), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+    hipLaunchKernelGGL(k_tp_split, dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+    hipLaunchKernelGGL(k_tp_place, dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
     return hipGetLastError();
 }
 
@@ -975,6 +1108,87 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
     if (lane == 0) publish(W, j, b, slot);
 }
 
+// Steps A-C, transposed probe, vector form: a quad of lanes per root; each
+// stream (row indices, mate columns, the row list of m_j) is read as the
+// 32-entry window that starts at the 16-byte boundary below the segment, one
+// 16-byte load per lane and half, all independent.  Entries outside the
+// segment are masked.  A segment that does not fit its window (or a window
+// that would pass the end of row_idx) takes the generic path.
+__device__ __forceinline__ int4 ld4(const int32_t* p) { return *reinterpret_cast<const int4*>(p); }
+
+__global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_threshold, int slot,
+                                                    const int32_t* __restrict__ roots,
+                                                    int32_t nroots) {
+    constexpr int T = 4, E = 8;
+    const int lane = threadIdx.x & 3;
+    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    int32_t j;
+    if (roots) {
+        if (tile >= nroots) return;  // tile-uniform
+        j = roots[tile];
+    } else {
+        if (tile >= A.n) return;
+        j = (int32_t)tile;
+    }
+    const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+    const int64_t len = hi - lo;
+    if (len > long_threshold) return;  // split kernel handles it
+    if (roots && lane == 0) W.dirty[j] = 0;
+    Cand b{0.0, INT32_MAX, -1, -1, -1};
+    if (len > 1) {
+        const int32_t mj = W.mc[j];
+        const double wmj = W.wm[j];
+        const int64_t rs = W.rstart[j];
+        const int32_t rlen = W.rlen[j];
+        const int64_t cb = lo & ~(int64_t)3, rb = rs & ~(int64_t)3;
+        if (hi <= cb + 32 && rs + rlen <= rb + 32 && cb + 32 <= A.nnz) {
+            const int4 i0 = ld4(A.row_idx + cb + 4 * lane), i1 = ld4(A.row_idx + cb + 16 + 4 * lane);
+            const int4 m0 = ld4(W.mrk + cb + 4 * lane), m1 = ld4(W.mrk + cb + 16 + 4 * lane);
+            const int4 r0 = ld4(W.colidx + rb + 4 * lane), r1 = ld4(W.colidx + rb + 16 + 4 * lane);
+            int32_t iv[E] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
+            int32_t mv[E] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+            int32_t rv[E] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t k = cb + 16 * (e >> 2) + 4 * lane + (e & 3);
+                const bool in = k >= lo && k < hi;
+                if (!(in && iv[e] > mj)) mv[e] = -1;
+                const int64_t x = rb + 16 * (e >> 2) + 4 * lane + (e & 3);
+                if (x < rs || x >= rs + rlen) rv[e] = -1;
+            }
+            int32_t qv[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) qv[e] = -1;
+#pragma unroll
+            for (int sft = 0; sft < T; ++sft) {
+#pragma unroll
+                for (int f = 0; f < E; ++f) {
+                    const int32_t v = __shfl_xor(rv[f], sft, T);
+                    const int32_t x = 16 * (f >> 2) + 4 * (lane ^ sft) + (f & 3);
+#pragma unroll
+                    for (int e = 0; e < E; ++e)
+                        if (mv[e] >= 0 && v == mv[e]) qv[e] = x;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (qv[e] >= 0) {
+                    const int64_t k = cb + 16 * (e >> 2) + 4 * lane + (e & 3);
+                    const int64_t p = W.cscpos[rb + qv[e]];
+                    const double g = (A.w[k] + A.w[p]) - (W.wm[mv[e]] + wmj);
+                    if (g > 0.0 && better(g, iv[e], b.g, b.i)) {
+                        b.g = g; b.i = iv[e]; b.c = mv[e]; b.k = k; b.p = p;
+                    }
+                }
+            }
+        } else {
+            root_generic<T, E>(A, W, lane, j, lo, hi, mj, wmj, rs, rlen, b);
+        }
+    }
+    reduce_best<T>(b);
+    if (lane == 0) publish(W, j, b, slot);
+}
+
 hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t long_threshold,
                          int slot, bool has_long, int probe, const int32_t* roots, int32_t nroots,
                          bool incremental, hipStream_t s, int cus) {
@@ -988,7 +1202,11 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
     else                                                                                    \
         hipLaunchKernelGGL(k_search_short<TW>, dim3(blocks), dim3(256), 0, s, A, W,         \
                            long_threshold, slot);
-    if (probe == 3) {
+    if (probe == 4) {
+        const unsigned vblocks = (unsigned)(((int64_t)(roots ? nroots : A.n) * 4 + 255) / 256);
+        hipLaunchKernelGGL(k_search_vec, dim3(vblocks), dim3(256), 0, s, A, W, long_threshold, slot,
+                           roots, nroots);
+    } else if (probe == 3) {
         switch (tile_width) {
             case 4: hipLaunchKernelGGL((k_search_chunk<4, 8>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, nroots); break;
             case 8: hipLaunchKernelGGL((k_search_chunk<8, 4>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, nroots); break;
@@ -1105,6 +1323,7 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.cand = (int32_t*)take(N * 4);
     W.long_list = (int32_t*)take(N * 4);
     W.chunk_off = (int64_t*)take((N + 1) * 8);
+    W.chunk_col = (int32_t*)take(max_chunks * 4);
     W.part_g = (double*)take(max_chunks * 8);
     W.part_i = (int32_t*)take(max_chunks * 4);
     W.part_c = (int32_t*)take(max_chunks * 4);
@@ -1119,9 +1338,9 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.rowptr = (int64_t*)take((N + 1) * 8);
     W.rstart = (int64_t*)take(N * 8);
     W.rlen = (int32_t*)take(N * 4);
-    W.colidx = (int32_t*)take(Z * 4);
+    W.colidx = (int32_t*)take(Z * 4 + 128);
     W.cscpos = (int64_t*)take(Z * 8);
-    W.mrk = (int32_t*)take(Z * 4);
+    W.mrk = (int32_t*)take(Z * 4 + 128);
     W.rowcnt = (int32_t*)take(N * 4);
     W.scan_sums = (int64_t*)take((N / 2048 + 2) * 8);
     W.flips = (int32_t*)take(N * 4 * 4 / 2 + 16);
@@ -1133,10 +1352,14 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.colof = (int32_t*)take(tpz * 4);
     W.tp_row = (int32_t*)take(tpz * 4);
     W.tp_col = (int32_t*)take(tpz * 4);
-    W.tp_pos = (int64_t*)take(tpz * 8);
+    W.tp_pos = (int32_t*)take(tpz * 4);
     W.tp_cnt = (int32_t*)take(tpm * 4);
     W.tp_off = (int64_t*)take((tpm + 1) * 8);
     W.tp_sums = (int64_t*)take((tpm / 2048 + 2) * 8);
+    W.tp_row2 = (int32_t*)take(tpz * 4);
+    W.tp_col2 = (int32_t*)take(tpz * 4);
+    W.tp_pos2 = (int32_t*)take(tpz * 4);
+    W.tp_sub = (int64_t*)take(P.ok ? (size_t)(P.nb * 64 + 1) * 8 : 0);
     Mcm M;
     M.mc = (int32_t*)take(N * 4);
     M.mr = (int32_t*)take(N * 4);

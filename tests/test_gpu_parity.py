@@ -95,9 +95,10 @@ def test_golden_on_gpu(solver, case):
 
 # search configurations: column binary search; transposed row lists; chunked
 # transposed (incremental rounds, the default); chunked with full rounds
-PROBES = ["p1", "p2", "p3", "p3full"]
+PROBES = ["p1", "p2", "p3", "p3full", "p4", "p4full"]
 _PROBE_KW = {"p1": dict(probe=1), "p2": dict(probe=2), "p3": dict(probe=3),
-             "p3full": dict(probe=3, full_search=True)}
+             "p3full": dict(probe=3, full_search=True), "p4": dict(probe=4),
+             "p4full": dict(probe=4, full_search=True)}
 
 
 @pytest.mark.parametrize("probe", PROBES)
@@ -115,8 +116,10 @@ def test_random_vs_oracle(solver, n, d, seed, intw, probe):
 @pytest.mark.parametrize("probe", PROBES)
 @pytest.mark.parametrize("tile", [4, 8, 16, 32, 64])
 def test_tile_widths_identical(solver, tile, probe):
-    if probe.startswith("p3") and tile == 64:
+    if probe[:2] in ("p3", "p4") and tile == 64:
         pytest.skip("the chunked kernel takes tiles of 4 to 32 lanes")
+    if probe[:2] == "p4" and tile != 4:
+        pytest.skip("the vector kernel always uses 4-lane tiles")
     wl = workload(0)
     run_both(solver, wl, tile_width=tile, **_PROBE_KW[probe])
     wl2 = small_random(5003, 30, 77, integer_weights=True, weight_range=1)  # heavy ties
@@ -177,7 +180,7 @@ def test_aliasing_and_determinism(solver):
     ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
     dev = solver.device
     cp, ri, w = _dev(wl.col_ptr, dev), _dev(wl.row_idx, dev), _dev(wl.w, dev)
-    for rep in range(4):
+    for rep in range(len(PROBES)):
         mate = _dev(wl.planted, dev)
         res = solver.improve(cp, ri, w, mate, perm_out=mate, **_PROBE_KW[PROBES[rep]])  # in place
         assert np.array_equal(mate.cpu().numpy(), ref.perm)

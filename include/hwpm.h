@@ -62,6 +62,7 @@ extern "C" {
 #define HWPM_ETOOBIG    -6  /* n or nnz beyond the library limits (n < 2^31 - 1, nnz < 2^40) */
 #define HWPM_EDEVICE    -7  /* a HIP runtime call failed (no device, launch failure, ...) */
 #define HWPM_EINTERNAL  -8  /* an internal consistency check failed (a bug) */
+#define HWPM_PENDING     1  /* hwpm_poll: the request has not finished yet (not an error) */
 
 #define HWPM_MAX_ROUND_STATS 512
 
@@ -221,6 +222,127 @@ int hwpm_improve(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32
  * untouched), else as hwpm_improve. */
 int hwpm_match(hwpm_handle h, const hwpm_csc* A, int32_t* perm_out, double* total_out,
                const hwpm_options* opt, hwpm_stats* stats, void* workspace, size_t workspace_bytes);
+
+/* ---- batches -------------------------------------------------------------
+ * Many matrices solved in one call.  The batch is packed into one
+ * block-diagonal matrix in the workspace and solved by the same kernels: no
+ * entry joins two blocks, so every cycle, Step-C choice and Step-D conflict
+ * stays inside its block and every matrix gets exactly the result it gets
+ * alone (a block whose rounds have ended has no candidates any more).  The
+ * number of kernel launches does not grow with the number of matrices. */
+typedef struct {
+    int32_t status;          /* HWPM_OK, or HWPM_ESINGULAR (hwpm_match_batch) */
+    int32_t rounds;          /* rounds this matrix would run alone */
+    int32_t hit_round_cap;
+    int32_t reserved;
+    int64_t cycles_applied;
+    double init_weight;      /* total weight of the starting matching */
+    double final_weight;     /* = totals[b] */
+} hwpm_item_stats;
+
+/* Workspace bytes for a batch: only n and nnz of each descriptor are used
+ * (its pointers are neither read nor checked).  HWPM_EINVAL for count < 0 or
+ * a negative size, HWPM_ETOOBIG beyond the limits. */
+int hwpm_batch_workspace_bytes(int32_t count, const hwpm_csc* mats, size_t* bytes);
+
+/* hwpm_improve on every matrix of a batch.
+ *   mats      host array of count CSC descriptors (their arrays on the device)
+ *   mate_in   host array of count device pointers (starting matchings)
+ *   perm_out  host array of count device pointers (results; may alias mate_in)
+ *   totals    host, nullable: count totals, each summed in its own tree
+ *   items     host, nullable: count per-matrix statistics
+ *   stats     host, nullable: statistics of the packed solve
+ * Errors as hwpm_improve, for the batch as a whole (a malformed matrix or
+ * matching fails the call; outputs untouched). */
+int hwpm_improve_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats,
+                       const int32_t* const* mate_in, int32_t* const* perm_out, double* totals,
+                       const hwpm_options* opt, hwpm_item_stats* items, hwpm_stats* stats,
+                       void* workspace, size_t workspace_bytes);
+
+/* hwpm_match on every matrix of a batch.  A structurally singular matrix does
+ * not fail the call: its item status is HWPM_ESINGULAR and its perm_out is
+ * left untouched. */
+int hwpm_match_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, int32_t* const* perm_out,
+                     double* totals, const hwpm_options* opt, hwpm_item_stats* items,
+                     hwpm_stats* stats, void* workspace, size_t workspace_bytes);
+
+/* ---- serving --------------------------------------------------------------
+ * A request loop for callers that produce a stream of independent matrices
+ * (e.g. a sparse direct solver that pivots every matrix it factorises).
+ * hwpm_submit takes a HOST CSC, validates it on the host and copies it into
+ * a FIFO queue.  Each worker owns a handle on its own HIP stream: whenever
+ * it is idle it admits, in arrival order, as many queued requests as fit into
+ * the free part of the server's device arena (their inputs, results and the
+ * batch workspace -- admission by HBM footprint), solves them as one
+ * hwpm_match_batch and hands back the results.  Requests that arrive while
+ * batches run join the next batch that has room (continuous batching), and
+ * the batches of different workers overlap on the device.  Results equal
+ * those of hwpm_match on each matrix alone.
+ *
+ * Ownership: the server allocates its arena (arena_bytes of device memory),
+ * one stream and handle per worker and the host copies of queued requests;
+ * hwpm_server_destroy finishes the queued requests and frees everything.
+ * hwpm_submit, hwpm_poll and hwpm_server_get_stats are thread-safe. */
+typedef struct hwpm_server_s* hwpm_server;
+
+typedef struct {
+    int32_t device;          /* HIP device ordinal */
+    int32_t workers;         /* worker streams, 1..16 */
+    int32_t max_batch;       /* most requests one batch admits, >= 1 */
+    int32_t reserved;
+    size_t arena_bytes;      /* device memory the server owns, >= 1 MiB */
+    hwpm_options solve;      /* options of every hwpm_match_batch call */
+} hwpm_server_options;
+
+typedef struct {
+    hwpm_item_stats item;    /* the request's statistics (item.status = its status) */
+    double queue_ms;         /* host clock: submit -> admitted into a batch */
+    double latency_ms;       /* host clock: submit -> result ready */
+    int32_t batch_size;      /* requests in the batch that solved it */
+    int32_t worker;          /* worker that solved it */
+} hwpm_request_info;
+
+typedef struct {
+    int64_t submitted;       /* requests accepted by hwpm_submit */
+    int64_t completed;       /* requests with a result (any status) */
+    int64_t batches;         /* batches launched */
+    int64_t max_batch_seen;  /* largest batch */
+    int64_t max_running;     /* most batches in flight at once */
+    int64_t pending;         /* requests waiting now */
+    int64_t running;         /* batches in flight now */
+    int64_t arena_in_use;    /* arena bytes held now */
+    int64_t arena_peak;      /* most arena bytes held at once */
+} hwpm_server_stats;
+
+/* Defaults: device 0, 2 workers, max_batch 64, 8 GiB arena, solve options
+ * from hwpm_default_options with check_csc = 0 (requests are validated on
+ * the host at submission). */
+void hwpm_server_default_options(hwpm_server_options* opt);
+
+/* Start a server (opt may be NULL for the defaults).  Errors: HWPM_EINVAL
+ * (bad option), HWPM_EDEVICE, HWPM_ENOMEM (arena allocation failed). */
+int hwpm_server_create(hwpm_server* out, const hwpm_server_options* opt);
+
+/* Finish every queued request, stop the workers and free the server.  Results
+ * not yet polled are discarded. */
+int hwpm_server_destroy(hwpm_server s);
+
+/* Queue one matrix; A holds HOST pointers and is copied before the call
+ * returns.  *ticket identifies the request in hwpm_poll.  Errors: HWPM_EINVAL,
+ * HWPM_ETOOBIG, HWPM_EBADCSC (the same checks as hwpm_check_csc, on the
+ * host); a rejected matrix is not queued. */
+int hwpm_submit(hwpm_server s, const hwpm_csc* A, uint64_t* ticket);
+
+/* Result of a request.  wait = 0 returns HWPM_PENDING at once if it has not
+ * finished; wait = 1 blocks until it has.  On completion returns the
+ * request's status (HWPM_OK, HWPM_ESINGULAR, HWPM_ETOOBIG when it cannot fit
+ * the arena even alone, or the batch's error), writes perm_host (host
+ * int32[n], nullable) and *total (nullable) when HWPM_OK, fills *info
+ * (nullable) and forgets the ticket.  An unknown ticket gives HWPM_EINVAL. */
+int hwpm_poll(hwpm_server s, uint64_t ticket, int32_t wait, int32_t* perm_host, double* total,
+              hwpm_request_info* info);
+
+int hwpm_server_get_stats(hwpm_server s, hwpm_server_stats* st);
 
 #ifdef __cplusplus
 }

@@ -9,13 +9,14 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhwpm.so")
-SOURCES = ["hwpm_api.hip", "hwpm_kernels.hip", "hwpm_mcm.hip"]
+SOURCES = ["hwpm_api.hip", "hwpm_kernels.hip", "hwpm_mcm.hip", "hwpm_batch.hip", "hwpm_server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
     "-O3",
     "-std=c++17",
     "-fPIC",
+    "-pthread",
     "-shared",
     "-ffp-contract=off",          # no fused multiply-add: fixed binary64 rounding
     "-fno-fast-math",

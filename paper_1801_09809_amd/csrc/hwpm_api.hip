@@ -3,6 +3,7 @@
 // hwpm_kernels.hip and reads back two counters per round.
 #include <chrono>
 #include <new>
+#include <vector>
 #include <string.h>
 
 #include "hwpm.h"
@@ -81,7 +82,8 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
 // The rounds of Section 5.3 from the perfect matching mate_in (CSC already
 // validated or trusted).  Fills the round statistics of *Sp.
 int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_in,
-                int32_t* perm_out, double* total_out, const hwpm_options& opt, hwpm_stats* Sp) {
+                int32_t* perm_out, double* total_out, const hwpm_options& opt, hwpm_stats* Sp,
+                const BatchPlan* BP = nullptr) {
     hwpm_stats& S = *Sp;
     const int32_t n = A.n;
     hipStream_t s = h->stream;
@@ -105,6 +107,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     HIP_TRY(hipStreamSynchronize(s));
     if (timing) S.ms_setup = elapsed(ev[0], ev[1]);
     if (h->host[kErrMatch]) return HWPM_EBADMATCH;
+    if (BP) HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_init, s, h->cus));
     const int32_t n_long = h->host[kNumLong];
     if (n_long > 0) HIP_TRY(launch_long_chunks(W, A, s));
     S.long_columns = n_long;
@@ -142,6 +145,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
         if (timing) HIP_TRY(hipEventRecord(ev[4], s));
         HIP_TRY(launch_apply(A, W, slot, transposed, s, h->cus));
         if (transposed) HIP_TRY(launch_mrk_update(W, slot, incremental, s, h->cus));
+        if (BP) HIP_TRY(launch_item_rounds(*BP, s));
         if (timing) HIP_TRY(hipEventRecord(ev[5], s));
         HIP_TRY(hipMemcpyAsync(h->host, W.counters + slot_word(slot, 0), kSlotWords * sizeof(int32_t),
                                hipMemcpyDeviceToHost, s));
@@ -176,6 +180,10 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     if (timing) HIP_TRY(hipEventRecord(ev[6], s));
     HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[0], s));
     HIP_TRY(hipMemcpyAsync(perm_out, W.mc, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (BP) {
+        HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_total, s, h->cus));
+        HIP_TRY(launch_unpack(*BP, W.mc, s, h->cus));
+    }
     HIP_TRY(hipMemcpyAsync(h->host + 8, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[7], s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -284,6 +292,163 @@ int run_initial_matching(hwpm_handle h, const Csc& A, const Work& W, const Mcm& 
     return unmatched == 0 ? HWPM_OK : HWPM_ESINGULAR;
 }
 
+
+// Host-side description of a batch: offsets and the chunk / tree-run tables.
+struct HostPlan {
+    std::vector<BatchItem> items;
+    std::vector<int32_t> col_chunk_item, ent_chunk_item, run_item;
+    std::vector<int64_t> col_chunk_first, ent_chunk_first, run_first, item_run0;
+    int64_t n_tot = 0, nnz_tot = 0;
+};
+
+constexpr int64_t kPackChunkHost = 4096;
+
+// sizes_only: plan from n and nnz alone (the pointers are neither read nor checked).
+int build_plan(int32_t count, const hwpm_csc* mats, const int32_t* const* mate_in,
+               int32_t* const* perm_out, HostPlan* HP, bool sizes_only = false) {
+    HP->items.resize(count);
+    for (int32_t b = 0; b < count; ++b) {
+        const hwpm_csc& A = mats[b];
+        if (A.n < 0 || A.nnz < 0) return HWPM_EINVAL;
+        if (!sizes_only && (!A.col_ptr || (A.nnz > 0 && (!A.row_idx || !A.weight)))) return HWPM_EINVAL;
+        if (A.n > 0 && perm_out && !perm_out[b]) return HWPM_EINVAL;
+        if (A.n > 0 && mate_in && !mate_in[b]) return HWPM_EINVAL;
+        BatchItem& it = HP->items[b];
+        it.col_ptr = A.col_ptr;
+        it.row_idx = A.row_idx;
+        it.w = A.weight;
+        it.mate_in = mate_in ? mate_in[b] : nullptr;
+        it.perm_out = perm_out ? perm_out[b] : nullptr;
+        it.n = A.n;
+        it.nnz = A.nnz;
+        it.col_off = HP->n_tot;
+        it.nnz_off = HP->nnz_tot;
+        for (int64_t j = 0; j < A.n; j += kPackChunkHost) {
+            HP->col_chunk_item.push_back(b);
+            HP->col_chunk_first.push_back(j);
+        }
+        for (int64_t k = 0; k < A.nnz; k += kPackChunkHost) {
+            HP->ent_chunk_item.push_back(b);
+            HP->ent_chunk_first.push_back(k);
+        }
+        HP->item_run0.push_back((int64_t)HP->run_item.size());
+        if (A.n > kTreeBlock) {
+            if (A.n > (int64_t)kTreeBlock * kTreeBlock) return HWPM_ETOOBIG;
+            for (int64_t r = 0; r < A.n; r += kTreeBlock) {
+                HP->run_item.push_back(b);
+                HP->run_first.push_back(r);
+            }
+        }
+        HP->n_tot += A.n;
+        HP->nnz_tot += A.nnz;
+    }
+    if (HP->n_tot >= INT32_MAX || HP->nnz_tot >= kMaxNnz) return HWPM_ETOOBIG;
+    return HWPM_OK;
+}
+
+size_t batch_layout(const HostPlan& HP, int32_t count, char* base, BatchPlan* out) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + off : nullptr;
+        off += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    BatchPlan P{};
+    P.count = count;
+    P.n_tot = HP.n_tot;
+    P.nnz_tot = HP.nnz_tot;
+    P.items = (BatchItem*)take(HP.items.size() * sizeof(BatchItem));
+    P.ncol_chunks = (int32_t)HP.col_chunk_item.size();
+    P.col_chunk_item = (int32_t*)take(HP.col_chunk_item.size() * 4);
+    P.col_chunk_first = (int64_t*)take(HP.col_chunk_first.size() * 8);
+    P.nent_chunks = (int32_t)HP.ent_chunk_item.size();
+    P.ent_chunk_item = (int32_t*)take(HP.ent_chunk_item.size() * 4);
+    P.ent_chunk_first = (int64_t*)take(HP.ent_chunk_first.size() * 8);
+    P.nruns = (int32_t)HP.run_item.size();
+    P.run_item = (int32_t*)take(HP.run_item.size() * 4);
+    P.run_first = (int64_t*)take(HP.run_first.size() * 8);
+    P.item_run0 = (int64_t*)take(HP.item_run0.size() * 8);
+    P.partial = (double*)take(HP.run_item.size() * 8 + 8);
+    P.col_ptr = (int64_t*)take((size_t)(HP.n_tot + 1) * 8);
+    P.row_idx = (int32_t*)take((size_t)HP.nnz_tot * 4);
+    P.w = (double*)take((size_t)HP.nnz_tot * 8);
+    P.mate = (int32_t*)take((size_t)HP.n_tot * 4);
+    P.mat_of_col = (int32_t*)take((size_t)HP.n_tot * 4);
+    P.item_flag = (int32_t*)take((size_t)count * 4);
+    P.item_rounds = (int32_t*)take((size_t)count * 4);
+    P.item_cycles = (unsigned long long*)take((size_t)count * 8);
+    P.item_unmatched = (int32_t*)take((size_t)count * 4);
+    P.item_err = (int32_t*)take(64);
+    P.item_total = (double*)take((size_t)count * 8);
+    P.item_init = (double*)take((size_t)count * 8);
+    if (out) *out = P;
+    return off;
+}
+
+// Copy the host tables into the batch region and clear the per-item counters.
+int upload_plan(hwpm_handle h, const HostPlan& HP, const BatchPlan& P) {
+    hipStream_t s = h->stream;
+    auto up = [&](void* dst, const void* src, size_t bytes) {
+        return bytes ? hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+    };
+    HIP_TRY(up(P.items, HP.items.data(), HP.items.size() * sizeof(BatchItem)));
+    HIP_TRY(up(P.col_chunk_item, HP.col_chunk_item.data(), HP.col_chunk_item.size() * 4));
+    HIP_TRY(up(P.col_chunk_first, HP.col_chunk_first.data(), HP.col_chunk_first.size() * 8));
+    HIP_TRY(up(P.ent_chunk_item, HP.ent_chunk_item.data(), HP.ent_chunk_item.size() * 4));
+    HIP_TRY(up(P.ent_chunk_first, HP.ent_chunk_first.data(), HP.ent_chunk_first.size() * 8));
+    HIP_TRY(up(P.run_item, HP.run_item.data(), HP.run_item.size() * 4));
+    HIP_TRY(up(P.run_first, HP.run_first.data(), HP.run_first.size() * 8));
+    HIP_TRY(up(P.item_run0, HP.item_run0.data(), HP.item_run0.size() * 8));
+    const size_t c = (size_t)P.count;
+    HIP_TRY(hipMemsetAsync(P.item_flag, 0, c * 4, s));
+    HIP_TRY(hipMemsetAsync(P.item_rounds, 0, c * 4, s));
+    HIP_TRY(hipMemsetAsync(P.item_cycles, 0, c * 8, s));
+    HIP_TRY(hipMemsetAsync(P.item_unmatched, 0, c * 4, s));
+    HIP_TRY(hipMemsetAsync(P.item_err, 0, 64, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the host tables may be released now
+    return HWPM_OK;
+}
+
+size_t batch_bytes(const HostPlan& HP, int32_t count) {
+    return batch_layout(HP, count, nullptr, nullptr) +
+           workspace_layout((int32_t)HP.n_tot, HP.nnz_tot, nullptr, nullptr);
+}
+
+// Per-item statistics after a packed solve (rounds reconstructed from the
+// rounds in which each block flipped cycles; a block alone stops after its
+// first round without flips, or at the cap).
+int fill_item_stats(hwpm_handle h, const BatchPlan& P, const hwpm_options& opt, double* totals,
+                    hwpm_item_stats* items) {
+    const size_t c = (size_t)P.count;
+    std::vector<int32_t> rounds(c);
+    std::vector<unsigned long long> cycles(c);
+    std::vector<double> tot(c), init(c);
+    HIP_TRY(hipMemcpyAsync(rounds.data(), P.item_rounds, c * 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(cycles.data(), P.item_cycles, c * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(tot.data(), P.item_total, c * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipMemcpyAsync(init.data(), P.item_init, c * 8, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    for (size_t b = 0; b < c; ++b) {
+        const int32_t a = rounds[b];
+        int32_t r = a + 1, cap = 0;
+        if (opt.max_rounds > 0 && a >= opt.max_rounds) {
+            r = opt.max_rounds;
+            cap = 1;
+        }
+        if (totals) totals[b] = tot[b];
+        if (items) {
+            items[b].status = HWPM_OK;
+            items[b].rounds = r;
+            items[b].hit_round_cap = cap;
+            items[b].reserved = 0;
+            items[b].cycles_applied = (int64_t)cycles[b];
+            items[b].init_weight = init[b];
+            items[b].final_weight = tot[b];
+        }
+    }
+    return HWPM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -310,6 +475,7 @@ const char* hwpm_strerror(int status) {
         case HWPM_ETOOBIG: return "matrix too large";
         case HWPM_EDEVICE: return "HIP runtime error";
         case HWPM_EINTERNAL: return "internal consistency check failed";
+        case HWPM_PENDING: return "request pending";
         default: return "unknown status";
     }
 }
@@ -460,5 +626,138 @@ int hwpm_match(hwpm_handle h, const hwpm_csc* Ain, int32_t* perm_out, double* to
     if (stats) *stats = S;
     return HWPM_OK;
 }
+
+int hwpm_batch_workspace_bytes(int32_t count, const hwpm_csc* mats, size_t* bytes) {
+    if (!bytes || count < 0 || (count > 0 && !mats)) return HWPM_EINVAL;
+    HostPlan HP;
+    const int st = build_plan(count, mats, nullptr, nullptr, &HP, true);
+    if (st != HWPM_OK) return st;
+    *bytes = batch_bytes(HP, count);
+    return HWPM_OK;
+}
+
+static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const int32_t* const* mate_in,
+                     int32_t* const* perm_out, double* totals, const hwpm_options* opt_in,
+                     hwpm_item_stats* items, hwpm_stats* stats, void* workspace, size_t workspace_bytes,
+                     bool match) {
+    const auto t_begin = std::chrono::steady_clock::now();
+    if (!h || count < 0 || (count > 0 && (!mats || !perm_out))) return HWPM_EINVAL;
+    if (!match && count > 0 && !mate_in) return HWPM_EINVAL;
+    hwpm_options opt;
+    hwpm_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    int st = check_options(opt);
+    if (st != HWPM_OK) return st;
+    HostPlan HP;
+    st = build_plan(count, mats, match ? nullptr : mate_in, perm_out, &HP);
+    if (st != HWPM_OK) return st;
+    hwpm_stats S;
+    memset(&S, 0, sizeof(S));
+    if (HP.n_tot == 0) {
+        for (int32_t b = 0; b < count; ++b) {
+            if (totals) totals[b] = 0.0;
+            if (items) memset(&items[b], 0, sizeof(hwpm_item_stats));
+        }
+        if (stats) *stats = S;
+        return HWPM_OK;
+    }
+    if (!workspace) return HWPM_EINVAL;
+    if (workspace_bytes < batch_bytes(HP, count)) return HWPM_ENOMEM;
+    DeviceGuard g(h->device);
+    if (!g.ok) return HWPM_EDEVICE;
+    BatchPlan P;
+    const size_t head = batch_layout(HP, count, (char*)workspace, &P);
+    char* rest = (char*)workspace + head;
+    Work W;
+    Mcm M;
+    workspace_layout((int32_t)HP.n_tot, HP.nnz_tot, rest, &W, &M);
+    W.mat_of_col = P.mat_of_col;
+    W.item_flag = P.item_flag;
+    W.item_cycles = P.item_cycles;
+    st = upload_plan(h, HP, P);
+    if (st != HWPM_OK) return st;
+    HIP_TRY(launch_pack(P, !match, h->stream, h->cus));
+    HIP_TRY(hipMemcpyAsync(h->host, P.item_err, sizeof(int32_t), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    Csc A;
+    A.n = (int32_t)HP.n_tot;
+    A.nnz = HP.nnz_tot;
+    A.col_ptr = P.col_ptr;
+    A.row_idx = P.row_idx;
+    A.w = P.w;
+    if (h->host[0] & 3) return HWPM_EBADCSC;
+    if (opt.check_csc) {
+        st = timed_check(h, A, W, opt.timing != 0, &S);
+        if (st != HWPM_OK) return st;
+    }
+    if (h->host[0] & 4) return HWPM_EBADMATCH;
+    const int32_t* start = P.mate;
+    if (match) {
+        st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, opt.timing != 0, &S);
+        if (st == HWPM_ESINGULAR) {
+            // some blocks have no perfect matching: solve the others one by one
+            std::vector<int32_t> unm(count);
+            HIP_TRY(launch_item_unmatched(P, M.mc, h->stream, h->cus));
+            HIP_TRY(hipMemcpyAsync(unm.data(), P.item_unmatched, (size_t)count * 4, hipMemcpyDeviceToHost,
+                                   h->stream));
+            HIP_TRY(hipStreamSynchronize(h->stream));
+            for (int32_t b = 0; b < count; ++b) {
+                if (unm[b] > 0) {
+                    if (items) {
+                        memset(&items[b], 0, sizeof(hwpm_item_stats));
+                        items[b].status = HWPM_ESINGULAR;
+                    }
+                    continue;
+                }
+                hwpm_stats Sb;
+                double tb = 0.0;
+                hwpm_options ob = opt;
+                ob.check_csc = 0;
+                const int sb = hwpm_match(h, &mats[b], perm_out[b], &tb, &ob, &Sb, rest,
+                                          workspace_bytes - head);
+                if (sb != HWPM_OK) return sb;
+                if (totals) totals[b] = tb;
+                if (items) {
+                    items[b].status = HWPM_OK;
+                    items[b].rounds = Sb.rounds;
+                    items[b].hit_round_cap = Sb.hit_round_cap;
+                    items[b].reserved = 0;
+                    items[b].cycles_applied = Sb.cycles_applied;
+                    items[b].init_weight = Sb.init_weight;
+                    items[b].final_weight = Sb.final_weight;
+                }
+            }
+            S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
+            if (stats) *stats = S;
+            return HWPM_OK;
+        }
+        if (st != HWPM_OK) return st;
+        start = M.mc;
+    }
+    double total = 0.0;
+    st = run_improve(h, A, W, start, P.mate, &total, opt, &S, &P);
+    if (st != HWPM_OK) return st;
+    st = fill_item_stats(h, P, opt, totals, items);
+    if (st != HWPM_OK) return st;
+    S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
+    if (stats) *stats = S;
+    return HWPM_OK;
+}
+
+int hwpm_improve_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const int32_t* const* mate_in,
+                       int32_t* const* perm_out, double* totals, const hwpm_options* opt,
+                       hwpm_item_stats* items, hwpm_stats* stats, void* workspace,
+                       size_t workspace_bytes) {
+    return run_batch(h, count, mats, mate_in, perm_out, totals, opt, items, stats, workspace,
+                     workspace_bytes, false);
+}
+
+int hwpm_match_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, int32_t* const* perm_out,
+                     double* totals, const hwpm_options* opt, hwpm_item_stats* items,
+                     hwpm_stats* stats, void* workspace, size_t workspace_bytes) {
+    return run_batch(h, count, mats, nullptr, perm_out, totals, opt, items, stats, workspace,
+                     workspace_bytes, true);
+}
+
 
 }  // extern "C"

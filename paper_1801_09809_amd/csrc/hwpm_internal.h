@@ -93,6 +93,49 @@ struct Work {
     int32_t* tp_col2;
     int32_t* tp_pos2;
     int64_t* tp_sub;    // start of every sub-bucket (+ total)
+    // batched solves (nullptr otherwise): the block of every packed column and
+    // per-block flip flags / counts
+    const int32_t* mat_of_col;
+    int32_t* item_flag;
+    unsigned long long* item_cycles;
+};
+
+// One matrix of a batch: its caller-owned device arrays and its place in the
+// packed block-diagonal matrix.
+struct BatchItem {
+    const int64_t* col_ptr;
+    const int32_t* row_idx;
+    const double* w;
+    const int32_t* mate_in;   // improve: starting matching; match: unused
+    int32_t* perm_out;
+    int64_t n;
+    int64_t nnz;
+    int64_t col_off;          // first packed column (= first packed row)
+    int64_t nnz_off;          // first packed entry
+};
+
+// Device-side tables of a batch (carved from the workspace; filled by the host).
+struct BatchPlan {
+    int32_t count;
+    int64_t n_tot, nnz_tot;
+    BatchItem* items;
+    int32_t* col_chunk_item; int64_t* col_chunk_first; int32_t ncol_chunks;
+    int32_t* ent_chunk_item; int64_t* ent_chunk_first; int32_t nent_chunks;
+    int32_t* run_item; int64_t* run_first; int32_t nruns;
+    int64_t* item_run0;       // first tree run of every item
+    double* partial;          // tree run sums
+    int64_t* col_ptr;         // packed matrix
+    int32_t* row_idx;
+    double* w;
+    int32_t* mate;
+    int32_t* mat_of_col;
+    int32_t* item_flag;
+    int32_t* item_rounds;
+    unsigned long long* item_cycles;
+    int32_t* item_unmatched;
+    int32_t* item_err;        // [0]: malformed input flags
+    double* item_total;
+    double* item_init;
 };
 
 // Counter words of the matching phase.
@@ -153,5 +196,10 @@ hipError_t launch_bfs_roots(const Csc& A, const Mcm& M, hipStream_t s, int cus);
 hipError_t launch_bfs_level(const Csc& A, const Mcm& M, const int32_t* fr, int32_t nf,
                             int32_t* next, int heavy, hipStream_t s, int cus);
 hipError_t launch_bfs_augment(const Csc& A, const Mcm& M, hipStream_t s, int cus);
+hipError_t launch_pack(const BatchPlan& P, bool with_mates, hipStream_t s, int cus);
+hipError_t launch_unpack(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus);
+hipError_t launch_seg_tree(const BatchPlan& P, const double* x, double* out, hipStream_t s, int cus);
+hipError_t launch_item_rounds(const BatchPlan& P, hipStream_t s);
+hipError_t launch_item_unmatched(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus);
 
 }  // namespace hwpm

@@ -417,6 +417,11 @@ __global__ void k_apply(Csc A, Work W, int slot, int transposed) {
             W.rstart[j] = sc; W.rlen[j] = lc;
             W.rstart[c] = sj; W.rlen[c] = lj;
         }
+        if (W.mat_of_col) {
+            const int32_t blk = W.mat_of_col[j];
+            W.item_flag[blk] = 1;
+            atomicAdd(&W.item_cycles[blk], 1ull);
+        }
         // the two rows whose mate changed, for the per-entry mate columns
         const int32_t q = atomicAdd(&W.counters[slot_word(slot, kApplied)], 1);
         W.flips[4 * (int64_t)q + 0] = i;
@@ -1309,7 +1314,7 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
         off += align_up(bytes);
         return p;
     };
-    Work W;
+    Work W{};
     W.mr = (int32_t*)take(N * 4);
     W.mc = (int32_t*)take(N * 4);
     W.wm = (double*)take(N * 8);
@@ -1379,6 +1384,9 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     M.level = (int32_t*)take(N * 4);
     M.counters = (int32_t*)take(kMcmWords * 4);
     if (mcm) *mcm = M;
+    W.mat_of_col = nullptr;
+    W.item_flag = nullptr;
+    W.item_cycles = nullptr;
     if (out) *out = W;
     return off;
 }

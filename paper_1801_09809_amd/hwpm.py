@@ -26,11 +26,15 @@ HWPM_ENOMEM = -5
 HWPM_ETOOBIG = -6
 HWPM_EDEVICE = -7
 HWPM_EINTERNAL = -8
+HWPM_PENDING = 1
 MAX_ROUND_STATS = 512
 
 EXPORTED = (
     "hwpm_default_options", "hwpm_strerror", "hwpm_create", "hwpm_destroy",
     "hwpm_workspace_bytes", "hwpm_check_csc", "hwpm_improve", "hwpm_match",
+    "hwpm_batch_workspace_bytes", "hwpm_improve_batch", "hwpm_match_batch",
+    "hwpm_server_default_options", "hwpm_server_create", "hwpm_server_destroy",
+    "hwpm_submit", "hwpm_poll", "hwpm_server_get_stats",
 )
 
 
@@ -104,6 +108,57 @@ class hwpm_stats(ctypes.Structure):
         return d
 
 
+class hwpm_item_stats(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("rounds", ctypes.c_int32),
+        ("hit_round_cap", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("cycles_applied", ctypes.c_int64),
+        ("init_weight", ctypes.c_double),
+        ("final_weight", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class hwpm_server_options(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("workers", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("arena_bytes", ctypes.c_size_t),
+        ("solve", hwpm_options),
+    ]
+
+
+class hwpm_request_info(ctypes.Structure):
+    _fields_ = [
+        ("item", hwpm_item_stats),
+        ("queue_ms", ctypes.c_double),
+        ("latency_ms", ctypes.c_double),
+        ("batch_size", ctypes.c_int32),
+        ("worker", ctypes.c_int32),
+    ]
+
+    def as_dict(self) -> dict:
+        d = self.item.as_dict()
+        d.update(queue_ms=self.queue_ms, latency_ms=self.latency_ms, batch_size=self.batch_size,
+                 worker=self.worker)
+        return d
+
+
+class hwpm_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "submitted", "completed", "batches", "max_batch_seen", "max_running", "pending", "running",
+        "arena_in_use", "arena_peak")]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -131,10 +186,32 @@ def load_library(path: str = LIB_PATH):
         lib.hwpm_match.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(hwpm_options), ctypes.POINTER(hwpm_stats), vp,
                                    ctypes.c_size_t]
+        lib.hwpm_batch_workspace_bytes.restype = ctypes.c_int
+        lib.hwpm_batch_workspace_bytes.argtypes = [i32, ctypes.POINTER(hwpm_csc), ctypes.POINTER(ctypes.c_size_t)]
+        batch_args = [vp, i32, ctypes.POINTER(hwpm_csc)]
+        tail = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(hwpm_options),
+                ctypes.POINTER(hwpm_item_stats), ctypes.POINTER(hwpm_stats), vp, ctypes.c_size_t]
+        lib.hwpm_improve_batch.restype = ctypes.c_int
+        lib.hwpm_improve_batch.argtypes = batch_args + [ctypes.POINTER(vp), ctypes.POINTER(vp)] + tail
+        lib.hwpm_match_batch.restype = ctypes.c_int
+        lib.hwpm_match_batch.argtypes = batch_args + [ctypes.POINTER(vp)] + tail
         lib.hwpm_improve.restype = ctypes.c_int
         lib.hwpm_improve.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, vp,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(hwpm_options),
                                      ctypes.POINTER(hwpm_stats), vp, ctypes.c_size_t]
+        lib.hwpm_server_default_options.restype = None
+        lib.hwpm_server_default_options.argtypes = [ctypes.POINTER(hwpm_server_options)]
+        lib.hwpm_server_create.restype = ctypes.c_int
+        lib.hwpm_server_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(hwpm_server_options)]
+        lib.hwpm_server_destroy.restype = ctypes.c_int
+        lib.hwpm_server_destroy.argtypes = [vp]
+        lib.hwpm_submit.restype = ctypes.c_int
+        lib.hwpm_submit.argtypes = [vp, ctypes.POINTER(hwpm_csc), ctypes.POINTER(ctypes.c_uint64)]
+        lib.hwpm_poll.restype = ctypes.c_int
+        lib.hwpm_poll.argtypes = [vp, ctypes.c_uint64, i32, vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(hwpm_request_info)]
+        lib.hwpm_server_get_stats.restype = ctypes.c_int
+        lib.hwpm_server_get_stats.argtypes = [vp, ctypes.POINTER(hwpm_server_stats)]
         _lib = lib
     return _lib
 
@@ -216,8 +293,105 @@ def hwpm_match(handle: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: int
     return st, total.value, stats
 
 
+def _csc_array(mats):
+    """mats: sequence of (n, nnz, col_ptr_ptr, row_idx_ptr, weight_ptr)."""
+    arr = (hwpm_csc * max(len(mats), 1))()
+    for b, m in enumerate(mats):
+        arr[b] = _csc(*m)
+    return arr
+
+
+def _ptr_array(ptrs):
+    arr = (ctypes.c_void_p * max(len(ptrs), 1))()
+    for b, p in enumerate(ptrs):
+        arr[b] = p
+    return arr
+
+
+def hwpm_batch_workspace_bytes(mats) -> int:
+    arr = _csc_array(mats)
+    b = ctypes.c_size_t(0)
+    st = load_library().hwpm_batch_workspace_bytes(len(mats), arr, ctypes.byref(b))
+    if st != HWPM_OK:
+        raise HwpmError(st, "hwpm_batch_workspace_bytes")
+    return int(b.value)
+
+
+def hwpm_improve_batch(handle: int, mats, mate_ptrs, perm_ptrs, ws_ptr: int, ws_bytes: int,
+                       options: hwpm_options | None = None):
+    """Returns (status, totals list, item stats array, batch stats)."""
+    count = len(mats)
+    totals = (ctypes.c_double * max(count, 1))()
+    items = (hwpm_item_stats * max(count, 1))()
+    stats = hwpm_stats()
+    st = load_library().hwpm_improve_batch(
+        ctypes.c_void_p(handle), count, _csc_array(mats), _ptr_array(mate_ptrs), _ptr_array(perm_ptrs),
+        totals, ctypes.byref(options) if options is not None else None, items, ctypes.byref(stats),
+        ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes))
+    return st, list(totals[:count]), items, stats
+
+
+def hwpm_match_batch(handle: int, mats, perm_ptrs, ws_ptr: int, ws_bytes: int,
+                     options: hwpm_options | None = None):
+    """Returns (status, totals list, item stats array, batch stats)."""
+    count = len(mats)
+    totals = (ctypes.c_double * max(count, 1))()
+    items = (hwpm_item_stats * max(count, 1))()
+    stats = hwpm_stats()
+    st = load_library().hwpm_match_batch(
+        ctypes.c_void_p(handle), count, _csc_array(mats), _ptr_array(perm_ptrs), totals,
+        ctypes.byref(options) if options is not None else None, items, ctypes.byref(stats),
+        ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes))
+    return st, list(totals[:count]), items, stats
+
+
+def hwpm_server_default_options() -> hwpm_server_options:
+    o = hwpm_server_options()
+    load_library().hwpm_server_default_options(ctypes.byref(o))
+    return o
+
+
+def hwpm_server_create(options: hwpm_server_options | None = None) -> int:
+    s = ctypes.c_void_p()
+    st = load_library().hwpm_server_create(ctypes.byref(s),
+                                           ctypes.byref(options) if options is not None else None)
+    if st != HWPM_OK:
+        raise HwpmError(st, "hwpm_server_create")
+    return s.value
+
+
+def hwpm_server_destroy(server: int) -> int:
+    return load_library().hwpm_server_destroy(ctypes.c_void_p(server))
+
+
+def hwpm_submit(server: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: int,
+                weight_ptr: int) -> tuple[int, int]:
+    """HOST pointers.  Returns (status, ticket)."""
+    t = ctypes.c_uint64(0)
+    A = _csc(n, nnz, col_ptr_ptr, row_idx_ptr, weight_ptr)
+    st = load_library().hwpm_submit(ctypes.c_void_p(server), ctypes.byref(A), ctypes.byref(t))
+    return st, int(t.value)
+
+
+def hwpm_poll(server: int, ticket: int, wait: bool, perm_ptr: int | None):
+    """perm_ptr: HOST int32[n] or None.  Returns (status, total, request info)."""
+    total = ctypes.c_double(0.0)
+    info = hwpm_request_info()
+    st = load_library().hwpm_poll(ctypes.c_void_p(server), ctypes.c_uint64(ticket), int(bool(wait)),
+                                  ctypes.c_void_p(perm_ptr or 0), ctypes.byref(total), ctypes.byref(info))
+    return st, total.value, info
+
+
+def hwpm_server_get_stats(server: int) -> hwpm_server_stats:
+    s = hwpm_server_stats()
+    st = load_library().hwpm_server_get_stats(ctypes.c_void_p(server), ctypes.byref(s))
+    if st != HWPM_OK:
+        raise HwpmError(st, "hwpm_server_get_stats")
+    return s
+
+
 # ---------------------------------------------------------------------------
-# convenience wrapper over torch tensors
+# convenience wrappers
 
 @dataclass
 class ImproveResult:
@@ -300,6 +474,37 @@ class Solver:
             raise HwpmError(st, "hwpm_match")
         return ImproveResult(perm_out, total, stats.as_dict())
 
+    def _batch(self, mats, mates, perms, match: bool, **kw):
+        desc = []
+        for (cp, ri, w) in mats:
+            self._check(cp, torch.int64, "col_ptr")
+            self._check(ri, torch.int32, "row_idx")
+            self._check(w, torch.float64, "w", ri.numel())
+            desc.append((cp.numel() - 1, ri.numel(), cp.data_ptr(), ri.data_ptr(), w.data_ptr()))
+        if perms is None:
+            perms = [torch.empty(d[0], dtype=torch.int32, device=self.device) for d in desc]
+        need = hwpm_batch_workspace_bytes(desc)
+        if self.ws.numel() < need:
+            self.ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
+        opt = self.options(**kw)
+        if match:
+            st, totals, items, stats = hwpm_match_batch(
+                self.handle, desc, [p.data_ptr() for p in perms], self.ws.data_ptr(), self.ws.numel(), opt)
+        else:
+            st, totals, items, stats = hwpm_improve_batch(
+                self.handle, desc, [m.data_ptr() for m in mates], [p.data_ptr() for p in perms],
+                self.ws.data_ptr(), self.ws.numel(), opt)
+        if st != HWPM_OK:
+            raise HwpmError(st, "hwpm_match_batch" if match else "hwpm_improve_batch")
+        return perms, totals, [items[b].as_dict() for b in range(len(desc))], stats.as_dict()
+
+    def improve_batch(self, mats, mates, perms=None, **kw):
+        """mats: list of (col_ptr, row_idx, w) device tensors; mates: starting matchings."""
+        return self._batch(mats, mates, perms, False, **kw)
+
+    def match_batch(self, mats, perms=None, **kw):
+        return self._batch(mats, None, perms, True, **kw)
+
     def improve(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
                 mate_in: torch.Tensor, perm_out: torch.Tensor | None = None, max_rounds: int = 0,
                 check_csc: bool = True, timing: bool = False, tile_width: int = 0,
@@ -321,3 +526,67 @@ class Solver:
         if st != HWPM_OK:
             raise HwpmError(st, "hwpm_improve")
         return ImproveResult(perm_out, total, stats.as_dict())
+
+
+class Server:
+    """Request loop over host matrices (numpy arrays): submit, then poll."""
+
+    def __init__(self, device: int = 0, workers: int = 2, max_batch: int = 64,
+                 arena_bytes: int = 8 << 30, **solve_kw):
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the HWPM library runs on the device only")
+        opt = hwpm_server_default_options()
+        opt.device = int(device)
+        opt.workers = int(workers)
+        opt.max_batch = int(max_batch)
+        opt.arena_bytes = int(arena_bytes)
+        if solve_kw:
+            solve_kw.setdefault("check_csc", False)
+            opt.solve = Solver.options(**solve_kw)
+        self.server = hwpm_server_create(opt)
+        self._n = {}
+
+    def close(self):
+        if self.server:
+            hwpm_server_destroy(self.server)
+            self.server = 0
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, col_ptr, row_idx, w) -> int:
+        import numpy as np
+        cp = np.ascontiguousarray(col_ptr, dtype=np.int64)
+        ri = np.ascontiguousarray(row_idx, dtype=np.int32)
+        ww = np.ascontiguousarray(w, dtype=np.float64)
+        n = cp.size - 1
+        if ww.size != ri.size:
+            raise ValueError("row_idx and w differ in length")
+        st, ticket = hwpm_submit(self.server, n, ri.size, cp.ctypes.data, ri.ctypes.data, ww.ctypes.data)
+        if st != HWPM_OK:
+            raise HwpmError(st, "hwpm_submit")
+        self._n[ticket] = n
+        return ticket
+
+    def poll(self, ticket: int, wait: bool = True):
+        """Returns None while pending, else (status, perm numpy int32 or None, total, info dict)."""
+        import numpy as np
+        n = self._n[ticket]
+        perm = np.empty(max(n, 1), dtype=np.int32)
+        st, total, info = hwpm_poll(self.server, ticket, wait, perm.ctypes.data)
+        if st == HWPM_PENDING:
+            return None
+        del self._n[ticket]
+        return st, (perm[:n] if st == HWPM_OK else None), total, info.as_dict()
+
+    def stats(self) -> dict:
+        return hwpm_server_get_stats(self.server).as_dict()

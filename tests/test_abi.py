@@ -4,6 +4,7 @@ without touching a device."""
 import ctypes
 import os
 import re
+import subprocess
 
 import pytest
 import torch
@@ -31,9 +32,11 @@ def test_library_exports_every_declared_symbol():
 
 def test_status_codes_match_header():
     text = open(HEADER).read()
-    for name, val in re.findall(r"#define (HWPM_E[A-Z]+|HWPM_OK)\s+(-?\d+)", text):
+    found = re.findall(r"#define (HWPM_E[A-Z]+|HWPM_OK|HWPM_PENDING)\s+(-?\d+)", text)
+    assert len(found) == 10
+    for name, val in found:
         assert getattr(hwpm, name) == int(val), name
-    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7, -8, 1):
         assert hwpm.hwpm_strerror(code) not in ("", "unknown status")
     assert hwpm.hwpm_strerror(12345) == "unknown status"
 
@@ -46,6 +49,63 @@ def test_struct_layouts():
     assert s.init_weight.offset == 40 and s.ms_check.offset == 56
     assert s.round_candidates.offset == 104
     assert ctypes.sizeof(s) == 104 + 4 * 4 * hwpm.MAX_ROUND_STATS
+
+
+_STRUCTS = ("hwpm_csc", "hwpm_options", "hwpm_stats", "hwpm_item_stats", "hwpm_server_options",
+            "hwpm_request_info", "hwpm_server_stats")
+
+
+def test_struct_layouts_match_the_c_compiler(tmp_path):
+    """Every field offset and struct size of the ctypes mirrors equals what gcc
+    lays out from include/hwpm.h."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "hwpm.h"', "int main(void) {"]
+    for sname in _STRUCTS:
+        cls = getattr(hwpm, sname)
+        lines.append(f'printf("{sname} sizeof %zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{sname} {fname} %zu\\n", offsetof({sname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    seen = 0
+    for line in out:
+        if not line:
+            continue
+        sname, fname, val = line.split()
+        cls = getattr(hwpm, sname)
+        got = ctypes.sizeof(cls) if fname == "sizeof" else getattr(cls, fname).offset
+        assert got == int(val), (sname, fname, got, val)
+        seen += 1
+    assert seen == sum(len(getattr(hwpm, s)._fields_) + 1 for s in _STRUCTS)
+
+
+def test_server_host_argument_checks():
+    lib = hwpm.load_library()
+    assert lib.hwpm_server_create(None, None) == hwpm.HWPM_EINVAL
+    o = hwpm.hwpm_server_default_options()
+    assert (o.workers, o.max_batch, o.arena_bytes, o.solve.check_csc) == (2, 64, 8 << 30, 0)
+    s = ctypes.c_void_p()
+    for field, bad in (("workers", 0), ("workers", 17), ("max_batch", 0), ("arena_bytes", 1000)):
+        ob = hwpm.hwpm_server_default_options()
+        setattr(ob, field, bad)
+        assert lib.hwpm_server_create(ctypes.byref(s), ctypes.byref(ob)) == hwpm.HWPM_EINVAL
+    st, _ = hwpm.hwpm_submit(0, 3, 3, 1, 1, 1)
+    assert st == hwpm.HWPM_EINVAL
+    st, _, _ = hwpm.hwpm_poll(0, 1, False, None)
+    assert st == hwpm.HWPM_EINVAL
+    assert hwpm.hwpm_server_destroy(0) == hwpm.HWPM_OK
+    assert lib.hwpm_server_get_stats(None, None) == hwpm.HWPM_EINVAL
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="needs a machine without a GPU")
+def test_server_without_device_fails_cleanly():
+    with pytest.raises(hwpm.HwpmError) as e:
+        hwpm.hwpm_server_create(None)
+    assert e.value.status == hwpm.HWPM_EDEVICE
 
 
 def test_default_options():

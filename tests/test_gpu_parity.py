@@ -398,3 +398,121 @@ def test_match_singular(solver):
 def test_match_full_workload(solver, k):
     wl = workload(k)
     match_both(solver, wl, check_csc=True)
+
+
+# ---------------------------------------------------------------------------
+# the paper's variants on the same kernels
+
+def test_variant_option_a_objective(solver):
+    """Sum of |a| instead of sum of log|a| (Option A): only the weights change."""
+    from workloads import option_a
+    for wl in (option_a(small_random(20011, 8, 41)), option_a(stencil27(19, 17, 13, 2105, 3105))):
+        run_both(solver, wl)
+        match_both(solver, wl)
+
+
+def test_variant_maxiters_10(solver):
+    """The paper's cap of 10 rounds, on an R-MAT matrix that needs more."""
+    wl = rmat(14, 16, 1014, 2014, 3014, name="rmat_scale14")
+    gpu, ref = run_both(solver, wl, max_rounds=10)
+    assert ref.hit_round_cap and gpu[2]["hit_round_cap"] == 1 and gpu[2]["rounds"] == 10
+    run_both(solver, wl, max_rounds=10, probe=1)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_variant_equilibrated_ties(solver, plain):
+    """Equilibrated matrices: the largest entry of every row and column has
+    weight exactly 0, so equal gains and equal proposal weights are common."""
+    from workloads import equilibrated
+    for wl in (equilibrated(small_random(30011, 6, 43)), equilibrated(stencil27(21, 21, 11, 2106, 3106))):
+        assert (wl.w == 0.0).sum() > wl.n // 2
+        if not plain:
+            run_both(solver, wl)
+            run_both(solver, wl, probe=1)
+        match_both(solver, wl, plain=plain)
+
+
+# ---------------------------------------------------------------------------
+# batches: every matrix gets exactly its own result
+
+def _mixed_batch(seed, count=9):
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        kind = b % 3
+        if kind == 0:
+            out.append(small_random(int(rng.integers(1, 3000)), int(rng.integers(1, 9)), seed * 100 + b,
+                                    integer_weights=bool(b % 2), weight_range=2))
+        elif kind == 1:
+            g = int(rng.integers(3, 14))
+            out.append(stencil27(g, g, g, seed * 100 + b, seed * 200 + b, n_keep=int(rng.integers(1, g ** 3 + 1))))
+        else:
+            out.append(rmat(int(rng.integers(6, 11)), 8, seed + b, seed + 2 * b, seed + 3 * b,
+                            name=f"rmat_small{b}"))
+    return out
+
+
+@pytest.mark.parametrize("probe", ["p1", "p3", "p4"])
+def test_improve_batch_equals_alone(solver, probe):
+    from oracle import oracle_improve
+    dev = solver.device
+    wls = _mixed_batch(5) + [small_random(1, 1, 3), workload(0)]
+    mats = [(_dev(w.col_ptr, dev), _dev(w.row_idx, dev), _dev(w.w, dev)) for w in wls]
+    mates = [_dev(w.planted, dev) for w in wls]
+    perms, totals, items, bst = solver.improve_batch(mats, mates, **_PROBE_KW[probe])
+    for wl, p, t, it in zip(wls, perms, totals, items):
+        ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
+        assert np.array_equal(p.cpu().numpy(), ref.perm), wl.name
+        assert np.float64(t).tobytes() == np.float64(ref.total).tobytes()
+        assert it["rounds"] == ref.rounds and it["cycles_applied"] == ref.cycles_applied
+        assert np.float64(it["init_weight"]).tobytes() == np.float64(ref.init_weight).tobytes()
+    assert bst["rounds"] == max(it["rounds"] for it in items)
+    # with a cap
+    perms, totals, items, _ = solver.improve_batch(mats, mates, max_rounds=2, **_PROBE_KW[probe])
+    for wl, p, t, it in zip(wls, perms, totals, items):
+        ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted, 2)
+        assert np.array_equal(p.cpu().numpy(), ref.perm) and t == ref.total
+        assert it["rounds"] == ref.rounds and it["hit_round_cap"] == int(ref.hit_round_cap)
+
+
+@pytest.mark.parametrize("plain", [False, True])
+def test_match_batch_equals_alone_with_singular(solver, plain):
+    from oracle import oracle_match
+    dev = solver.device
+    wls = _mixed_batch(7)
+    # a structurally singular member: its last row is empty
+    nan = np.nan
+    wls.insert(3, from_dense(np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0], [nan, nan, nan]]),
+                             name="singular3"))
+    mats = [(_dev(w.col_ptr, dev), _dev(w.row_idx, dev), _dev(w.w, dev)) for w in wls]
+    perms = [torch.full((w.n,), -7, dtype=torch.int32, device=dev) for w in wls]
+    perms, totals, items, _ = solver.match_batch(mats, perms=perms, mcm_plain=plain)
+    for wl, p, t, it in zip(wls, perms, totals, items):
+        ref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w, heavy=not plain)
+        if ref.status == -2:
+            assert it["status"] == -2 and (p.cpu().numpy() == -7).all(), wl.name
+            continue
+        assert it["status"] == 0
+        assert np.array_equal(p.cpu().numpy(), ref.perm), wl.name
+        assert np.float64(t).tobytes() == np.float64(ref.total).tobytes()
+        assert it["rounds"] == ref.rounds
+
+
+def test_batch_rejects_bad_member(solver):
+    from paper_1801_09809_amd import hwpm
+    dev = solver.device
+    good, bad = small_random(300, 3, 1), small_random(200, 3, 2)
+    ri = bad.row_idx.copy(); ri[10] = 250  # inside the packed range, outside its block
+    mats = [(_dev(good.col_ptr, dev), _dev(good.row_idx, dev), _dev(good.w, dev)),
+            (_dev(bad.col_ptr, dev), _dev(ri, dev), _dev(bad.w, dev))]
+    mates = [_dev(good.planted, dev), _dev(bad.planted, dev)]
+    with pytest.raises(hwpm.HwpmError) as e:
+        solver.improve_batch(mats, mates, check_csc=False)
+    assert e.value.status == hwpm.HWPM_EBADCSC
+    m2 = bad.planted.copy(); m2[0] = 200
+    mats[1] = (_dev(bad.col_ptr, dev), _dev(bad.row_idx, dev), _dev(bad.w, dev))
+    with pytest.raises(hwpm.HwpmError) as e:
+        solver.improve_batch(mats, [mates[0], _dev(m2, dev)])
+    assert e.value.status == hwpm.HWPM_EBADMATCH
+    perms, totals, items, _ = solver.improve_batch([], [])
+    assert perms == [] and totals == []

@@ -1,0 +1,158 @@
+"""GPU tests of the serving form (hwpm_submit / hwpm_poll): every served
+result equals the oracle's hwpm_match result for that matrix alone, bit for
+bit, however the requests were batched, admitted or spread over workers."""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle_match  # noqa: E402
+from workloads import from_dense, rmat, small_random, stencil27  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1801_09809_amd import hwpm
+    return hwpm
+
+
+def _requests(seed, count):
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(count):
+        kind = b % 4
+        if kind == 0:
+            out.append(small_random(int(rng.integers(1, 2500)), int(rng.integers(1, 7)), seed * 1000 + b,
+                                    integer_weights=bool(b % 3 == 0), weight_range=2))
+        elif kind == 1:
+            g = int(rng.integers(3, 12))
+            out.append(stencil27(g, g, g, seed * 1000 + b, seed * 2000 + b,
+                                 n_keep=int(rng.integers(1, g ** 3 + 1))))
+        elif kind == 2:
+            out.append(rmat(int(rng.integers(5, 10)), 8, seed + b, seed + 2 * b, seed + 3 * b,
+                            name=f"rmat_srv{b}"))
+        else:
+            out.append(small_random(int(rng.integers(1, 40)), 2, seed * 1000 + b))
+    return out
+
+
+def _check(wl, res, plain=False):
+    st, perm, total, info = res
+    ref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w, heavy=not plain)
+    if ref.status == -2:
+        assert st == -2 and perm is None, wl.name
+        return
+    assert st == 0, (wl.name, st)
+    assert np.array_equal(perm, ref.perm), wl.name
+    assert np.float64(total).tobytes() == np.float64(ref.total).tobytes(), wl.name
+    assert info["rounds"] == ref.rounds and info["cycles_applied"] == ref.cycles_applied
+    assert info["latency_ms"] >= info["queue_ms"] >= 0.0
+    assert info["batch_size"] >= 1
+
+
+@pytest.mark.parametrize("workers,max_batch", [(1, 64), (2, 64), (4, 8), (1, 1)])
+def test_served_equals_oracle(workers, max_batch):
+    hwpm = _need_gpu()
+    wls = _requests(11 + workers, 24)
+    nan = np.nan
+    wls.insert(5, from_dense(np.array([[1.0, 2.0, 3.0], [4.0, 5.0, 6.0], [nan, nan, nan]]),
+                             name="singular3"))
+    wls.insert(9, small_random(0, 1, 1))
+    print(f"[gpu] server workers={workers} max_batch={max_batch} requests={len(wls)}", flush=True)
+    with hwpm.Server(workers=workers, max_batch=max_batch, arena_bytes=256 << 20) as srv:
+        tickets = [srv.submit(w.col_ptr, w.row_idx, w.w) for w in wls]
+        results = [srv.poll(t) for t in tickets]
+        stats = srv.stats()
+    for wl, res in zip(wls, results):
+        _check(wl, res)
+    assert stats["submitted"] == stats["completed"] == len(wls)
+    assert stats["pending"] == 0 and stats["running"] == 0 and stats["arena_in_use"] == 0
+    assert stats["max_batch_seen"] <= max_batch
+    assert 0 < stats["arena_peak"] <= 256 << 20
+    if max_batch == 1:
+        assert stats["batches"] == len(wls)
+
+
+def test_continuous_batching_admits_waiting_requests():
+    """With one worker, requests that arrive while a batch runs are packed
+    into the next batch (their footprint permitting)."""
+    hwpm = _need_gpu()
+    big = stencil27(40, 40, 40, 7, 8, name="stencil_40cubed")
+    small = _requests(3, 30)
+    with hwpm.Server(workers=1, max_batch=64, arena_bytes=1 << 30) as srv:
+        t0 = srv.submit(big.col_ptr, big.row_idx, big.w)
+        ts = [srv.submit(w.col_ptr, w.row_idx, w.w) for w in small]
+        results = [srv.poll(t) for t in [t0] + ts]
+        stats = srv.stats()
+    for wl, res in zip([big] + small, results):
+        _check(wl, res)
+    assert stats["batches"] < 1 + len(small)
+    assert stats["max_batch_seen"] > 1
+
+
+def test_admission_by_footprint():
+    """An arena that holds about one request at a time still serves them all,
+    one batch each; a request larger than the arena fails alone."""
+    hwpm = _need_gpu()
+    from paper_1801_09809_amd.hwpm import hwpm_batch_workspace_bytes
+    wls = [small_random(3000, 6, 40 + b) for b in range(4)]
+    one = hwpm_batch_workspace_bytes([(w.n, w.nnz, 0, 0, 0) for w in wls[:1]])
+    arena = one + (1 << 20)  # one request and its inputs; never two
+    huge = small_random(60000, 8, 99)
+    with hwpm.Server(workers=2, max_batch=64, arena_bytes=arena) as srv:
+        ts = [srv.submit(w.col_ptr, w.row_idx, w.w) for w in wls]
+        th = srv.submit(huge.col_ptr, huge.row_idx, huge.w)
+        results = [srv.poll(t) for t in ts]
+        rh = srv.poll(th)
+        stats = srv.stats()
+    for wl, res in zip(wls, results):
+        _check(wl, res)
+    assert rh[0] == hwpm.HWPM_ETOOBIG and rh[1] is None
+    assert stats["max_batch_seen"] == 1 and stats["batches"] == len(wls)
+    assert stats["arena_peak"] <= arena
+
+
+def test_submit_rejects_bad_matrix_and_poll_semantics():
+    hwpm = _need_gpu()
+    good = small_random(500, 4, 5)
+    bad = small_random(400, 4, 6)
+    ri = bad.row_idx.copy()
+    ri[3] = 400  # row out of range
+    unsorted = bad.row_idx.copy()
+    c0 = int(np.argmax(np.diff(bad.col_ptr) >= 2))
+    k = int(bad.col_ptr[c0])
+    unsorted[k], unsorted[k + 1] = unsorted[k + 1], unsorted[k]
+    wnan = bad.w.copy()
+    wnan[7] = np.nan
+    with hwpm.Server(workers=1) as srv:
+        for r, w in ((ri, bad.w), (unsorted, bad.w), (bad.row_idx, wnan)):
+            with pytest.raises(hwpm.HwpmError) as e:
+                srv.submit(bad.col_ptr, r, w)
+            assert e.value.status == hwpm.HWPM_EBADCSC
+        t = srv.submit(good.col_ptr, good.row_idx, good.w)
+        res = None
+        deadline = time.time() + 60
+        while res is None and time.time() < deadline:
+            res = srv.poll(t, wait=False)
+            if res is None:
+                time.sleep(0.001)
+        assert res is not None
+        _check(good, res)
+        st, _, _ = hwpm.hwpm_poll(srv.server, t, True, None)  # already delivered
+        assert st == hwpm.HWPM_EINVAL
+        st, _, _ = hwpm.hwpm_poll(srv.server, 987654321, False, None)
+        assert st == hwpm.HWPM_EINVAL
+
+
+def test_destroy_finishes_queued_requests():
+    hwpm = _need_gpu()
+    wls = _requests(9, 12)
+    srv = hwpm.Server(workers=2, max_batch=4, arena_bytes=128 << 20)
+    for w in wls:
+        srv.submit(w.col_ptr, w.row_idx, w.w)
+    srv.close()  # joins the workers after the queue drains

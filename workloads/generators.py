@@ -219,3 +219,64 @@ def from_dense(a: np.ndarray, planted=None, name: str = "dense") -> Workload:
         planted = np.arange(n, dtype=np.int32)
     return Workload(name, n, col_ptr, row_idx, np.ascontiguousarray(w, dtype=np.float64),
                     np.asarray(planted, dtype=np.int32))
+
+
+def magnitudes(wl: Workload) -> np.ndarray:
+    """|a_ij| of a workload whose weights are log|a_ij| (the inverse map)."""
+    return np.exp(wl.w)
+
+
+def with_weights(wl: Workload, w: np.ndarray, suffix: str) -> Workload:
+    return Workload(wl.name + suffix, wl.n, wl.col_ptr, wl.row_idx,
+                    np.ascontiguousarray(w, dtype=np.float64), wl.planted)
+
+
+def option_a(wl: Workload) -> Workload:
+    """The sum objective ("Option A"): weights |a_ij| instead of log|a_ij|."""
+    return with_weights(wl, magnitudes(wl), "_sum")
+
+
+def equilibrated(wl: Workload) -> Workload:
+    """Diagonal scaling so that the largest magnitude of every row, then of
+    every column, is 1 (the preprocessing the paper applies before matching);
+    weights log of the scaled magnitudes, so many are exactly 0."""
+    a = magnitudes(wl)
+    cols = np.repeat(np.arange(wl.n), np.diff(wl.col_ptr))
+    rmax = np.zeros(wl.n)
+    np.maximum.at(rmax, wl.row_idx, a)
+    a = a / rmax[wl.row_idx]
+    cmax = np.zeros(wl.n)
+    np.maximum.at(cmax, cols, a)
+    a = a / cmax[cols]
+    return with_weights(wl, np.log(a), "_equil")
+
+
+# --------------------------------------------------------------------------
+# The serving stream: many matrices of uneven size.
+
+SERVING_SEED = 4000
+
+
+def serving_matrix(index: int, seed: int = SERVING_SEED) -> Workload:
+    """Matrix `index` of the serving stream: n = round(10**U(2, 5)); with
+    probability 1/2 the random generator of workload 0 (8 rows per column plus
+    the diagonal), else a 27-point stencil on a g x g x h box with
+    g = floor(cbrt(n)), h = ceil(n / g**2), cut to its leading n x n block,
+    with workload 2's value distribution.  Every draw of matrix `index` comes
+    from generators seeded by (seed, index) alone, so any subset of the stream
+    can be generated independently."""
+    rs = np.random.Generator(np.random.PCG64([seed, index]))
+    n = int(round(10.0 ** rs.uniform(2.0, 5.0)))
+    s1, s2, s3 = (int(x) for x in rs.integers(0, 2 ** 62, size=3))
+    if rs.random() < 0.5:
+        return random_matrix(n, 8, s1, s2, s3, name=f"serve{index}_random_n{n}")
+    g = max(1, int(np.floor(np.cbrt(n) + 1e-9)))
+    h = -(-n // (g * g))
+    return stencil27(g, g, h, s2, s3, name=f"serve{index}_stencil_n{n}", n_keep=n)
+
+
+def poisson_arrivals(count: int, rate: float, seed: int = SERVING_SEED) -> np.ndarray:
+    """Arrival times (seconds from the start) of a Poisson process of the given
+    rate: cumulative sums of seeded exponential gaps."""
+    gaps = np.random.Generator(np.random.PCG64([seed, 1 << 40])).exponential(1.0 / rate, size=count)
+    return np.cumsum(gaps)

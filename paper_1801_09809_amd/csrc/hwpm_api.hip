@@ -417,8 +417,8 @@ size_t batch_bytes(const HostPlan& HP, int32_t count) {
 // Per-item statistics after a packed solve (rounds reconstructed from the
 // rounds in which each block flipped cycles; a block alone stops after its
 // first round without flips, or at the cap).
-int fill_item_stats(hwpm_handle h, const BatchPlan& P, const hwpm_options& opt, double* totals,
-                    hwpm_item_stats* items) {
+int fill_item_stats(hwpm_handle h, const HostPlan& HP, const BatchPlan& P, const hwpm_options& opt,
+                    double* totals, hwpm_item_stats* items) {
     const size_t c = (size_t)P.count;
     std::vector<int32_t> rounds(c);
     std::vector<unsigned long long> cycles(c);
@@ -430,7 +430,9 @@ int fill_item_stats(hwpm_handle h, const BatchPlan& P, const hwpm_options& opt, 
     HIP_TRY(hipStreamSynchronize(h->stream));
     for (size_t b = 0; b < c; ++b) {
         const int32_t a = rounds[b];
-        int32_t r = a + 1, cap = 0;
+        // alone, an empty matrix runs no search pass at all; any other runs
+        // one pass per round that flipped cycles, plus the pass that finds none
+        int32_t r = HP.items[b].n > 0 ? a + 1 : 0, cap = 0;
         if (opt.max_rounds > 0 && a >= opt.max_rounds) {
             r = opt.max_rounds;
             cap = 1;
@@ -737,7 +739,7 @@ static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const i
     double total = 0.0;
     st = run_improve(h, A, W, start, P.mate, &total, opt, &S, &P);
     if (st != HWPM_OK) return st;
-    st = fill_item_stats(h, P, opt, totals, items);
+    st = fill_item_stats(h, HP, P, opt, totals, items);
     if (st != HWPM_OK) return st;
     S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
     if (stats) *stats = S;

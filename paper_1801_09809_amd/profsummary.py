@@ -1,16 +1,29 @@
-"""Summarise a rocprofv3 results database (kernel trace, optional counters)
-into a short text table for the profiles/ folder.
+"""Summarise rocprofv3 results databases into short text for the profiles/
+folder, and derive the HBM traffic of a kernel from two counter passes.
 
-    python -m paper_1801_09809_amd.profsummary RESULTS.db --command "..." > profiles/X.txt
+    python -m paper_1801_09809_amd.profsummary trace RESULTS.db --command "..."
+    python -m paper_1801_09809_amd.profsummary traffic --fetch FETCH.db --write WRITE.db \
+        --kernel k_search_chunk --copy-bytes N --source csrc/hwpm_kernels.hip --out profiles/traffic.json
 
-Reads only the SQLite file rocprofv3 writes (views `kernels`, `pmc_events`).
+Reads only the SQLite files rocprofv3 writes (views `kernels` and
+`counters_collection`).  Counter values are summed over the rows of one
+dispatch, then averaged over the dispatches of a kernel.
+
+Traffic calibration: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) are scaled
+by what the same counters read for the runtime's device-to-device copy kernel
+of a known size in the same run (algorithmic bytes / counted bytes), so the
+figure is in true HBM bytes.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
+import json
 import sqlite3
 import sys
 from collections import defaultdict
+
+COPY_KERNEL = "__amd_rocclr_copyBuffer"
 
 
 def kernel_table(con):
@@ -22,21 +35,36 @@ def kernel_table(con):
 
 
 def counter_table(con):
+    """{kernel name: {counter: (average per dispatch, dispatches)}}; per dispatch,
+    values of the same counter are summed."""
     try:
         rows = con.execute(
-            "select k.name, p.counter_name, avg(p.value), count(*) from pmc_events p "
-            "join kernels k on p.event_id = k.event_id group by k.name, p.counter_name").fetchall()
+            "select kernel_name, counter_name, dispatch_id, sum(value) from counters_collection "
+            "group by kernel_name, counter_name, dispatch_id").fetchall()
     except sqlite3.Error:
-        return []
-    return rows
+        return {}
+    acc = defaultdict(lambda: defaultdict(list))
+    for name, cname, _disp, val in rows:
+        acc[name][cname].append(val)
+    return {name: {c: (sum(v) / len(v), len(v)) for c, v in d.items()} for name, d in acc.items()}
 
 
-def main(argv=None) -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("db")
-    ap.add_argument("--command", default="", help="the command that produced the database")
-    ap.add_argument("--top", type=int, default=20)
-    args = ap.parse_args(argv)
+def dispatch_values(con, counter):
+    """[(kernel name, value)] per dispatch, in dispatch order."""
+    rows = con.execute(
+        "select kernel_name, dispatch_id, sum(value) from counters_collection where counter_name = ? "
+        "group by dispatch_id order by dispatch_id", (counter,)).fetchall()
+    return [(name, val) for name, _d, val in rows]
+
+
+def match_kernel(names, key):
+    hits = sorted({n for n in names if key in n})
+    if len(hits) != 1:
+        raise SystemExit(f"kernel key {key!r} matches {hits}")
+    return hits[0]
+
+
+def cmd_trace(args) -> int:
     con = sqlite3.connect(args.db)
     if args.command:
         print(f"command: {args.command}")
@@ -48,13 +76,71 @@ def main(argv=None) -> int:
     ct = counter_table(con)
     if ct:
         print("\ncounters (average per dispatch)")
-        by = defaultdict(dict)
-        for name, cname, val, cnt in ct:
-            by[name][cname] = (val, cnt)
-        for name, d in by.items():
+        for name, d in ct.items():
             vals = ", ".join(f"{c}={v:.6g} (n={n})" for c, (v, n) in sorted(d.items()))
             print(f"  {name[:90]}: {vals}")
     return 0
+
+
+def _calibrated(db, counter, kernel_key, copy_bytes):
+    con = sqlite3.connect(db)
+    vals = dispatch_values(con, counter)
+    if not vals:
+        raise SystemExit(f"{db}: no {counter} values")
+    kname = match_kernel({n for n, _ in vals}, kernel_key)
+    kv = [v for n, v in vals if n == kname]
+    # the calibration copies are the largest copy-kernel dispatches
+    cv = sorted((v for n, v in vals if n.startswith(COPY_KERNEL)), reverse=True)[:3]
+    if not cv:
+        raise SystemExit(f"{db}: no {COPY_KERNEL} dispatch to calibrate with")
+    copy_kib = sum(cv) / len(cv)
+    factor = (copy_bytes / 1024.0) / copy_kib
+    per_launch_kib = sum(kv) / len(kv)
+    return kname, per_launch_kib, copy_kib, factor, len(kv)
+
+
+def cmd_traffic(args) -> int:
+    kname, f_kib, f_copy, f_fac, nf = _calibrated(args.fetch, "FETCH_SIZE", args.kernel, args.copy_bytes)
+    _, w_kib, w_copy, w_fac, nw = _calibrated(args.write, "WRITE_SIZE", args.kernel, args.copy_bytes)
+    sha = hashlib.sha256(open(args.source, "rb").read()).hexdigest()[:16]
+    read_b = f_kib * 1024.0 * f_fac
+    write_b = w_kib * 1024.0 * w_fac
+    rec = {"kernel": kname, "kernel_src_sha": sha, "bytes_per_launch": read_b + write_b,
+           "read_bytes_per_launch": read_b, "write_bytes_per_launch": write_b,
+           "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib, "dispatches": [nf, nw],
+           "copy_bytes": args.copy_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
+           "fetch_factor": f_fac, "write_factor": w_fac, "command": args.command}
+    data = {}
+    try:
+        with open(args.out) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        pass
+    data[args.kernel] = rec
+    with open(args.out, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(rec, indent=1))
+    return 0
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("trace")
+    t.add_argument("db")
+    t.add_argument("--command", default="", help="the command that produced the database")
+    t.add_argument("--top", type=int, default=25)
+    r = sub.add_parser("traffic")
+    r.add_argument("--fetch", required=True, help="database of the FETCH_SIZE pass")
+    r.add_argument("--write", required=True, help="database of the WRITE_SIZE pass")
+    r.add_argument("--kernel", required=True, help="substring naming one kernel")
+    r.add_argument("--copy-bytes", type=int, required=True, help="bytes of each calibration copy")
+    r.add_argument("--source", required=True, help="source file of the kernel (its hash is recorded)")
+    r.add_argument("--out", required=True)
+    r.add_argument("--command", default="")
+    args = ap.parse_args(argv)
+    return cmd_trace(args) if args.cmd == "trace" else cmd_traffic(args)
 
 
 if __name__ == "__main__":

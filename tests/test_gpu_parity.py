@@ -456,7 +456,8 @@ def _mixed_batch(seed, count=9):
 def test_improve_batch_equals_alone(solver, probe):
     from oracle import oracle_improve
     dev = solver.device
-    wls = _mixed_batch(5) + [small_random(1, 1, 3), workload(0)]
+    # an empty member runs no search pass (rounds 0), as alone
+    wls = _mixed_batch(5) + [small_random(1, 1, 3), small_random(0, 1, 1), workload(0)]
     mats = [(_dev(w.col_ptr, dev), _dev(w.row_idx, dev), _dev(w.w, dev)) for w in wls]
     mates = [_dev(w.planted, dev) for w in wls]
     perms, totals, items, bst = solver.improve_batch(mats, mates, **_PROBE_KW[probe])

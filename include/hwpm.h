@@ -131,7 +131,7 @@ typedef struct {
     float ms_setup;          /* matching validation, mate/weight arrays, long-column table */
     float ms_transpose;      /* pattern transpose + per-entry mate columns (probe >= 2) */
     float ms_search;         /* Steps A-C (cycle search + per-root argmax), all rounds */
-    float ms_resolve;        /* Step D conflict resolution, all rounds */
+    float ms_resolve;        /* Step D conflict resolution (both passes), all rounds */
     float ms_apply;          /* flips (and mate-column updates), all rounds */
     float ms_final;          /* total weight + output copy */
     float ms_total;          /* whole call, host wall clock */
@@ -222,6 +222,20 @@ int hwpm_improve(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32
  * untouched), else as hwpm_improve. */
 int hwpm_match(hwpm_handle h, const hwpm_csc* A, int32_t* perm_out, double* total_out,
                const hwpm_options* opt, hwpm_stats* stats, void* workspace, size_t workspace_bytes);
+
+/* ---- tuning ---------------------------------------------------------------
+ * Launch-configuration tuner.  Runs hwpm_improve from mate_in once per
+ * candidate (probe, tile_width) -- probe 1 with tiles 4, 8, 16, 32, 64,
+ * probe 3 with tiles 4, 8, 16, 32, and probe 4 -- twice over, timing each
+ * whole call on the host clock, and writes the fastest candidate's probe and
+ * tile_width into *opt (its other fields are used as given: max_rounds,
+ * full_search, ...).  Outputs never depend on these two fields, so a tuned
+ * solve returns exactly what an untuned one does; perm_out holds that result
+ * (device int32[n]).  ms_out (host, nullable) receives the best time of each
+ * candidate, in the order above.  Errors as hwpm_improve. */
+#define HWPM_TUNE_CANDIDATES 10
+int hwpm_autotune(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
+                  hwpm_options* opt, float* ms_out, void* workspace, size_t workspace_bytes);
 
 /* ---- batches -------------------------------------------------------------
  * Many matrices solved in one call.  The batch is packed into one

@@ -139,8 +139,8 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
         if (!listed || nroots > 0)
             HIP_TRY(launch_search(A, W, tile, kLongThreshold, slot, n_long > 0, probe,
                                   listed ? W.dirty_list : nullptr, nroots, incremental, s, h->cus));
-        HIP_TRY(launch_collect(A, W, slot, s, h->cus));
         if (timing) HIP_TRY(hipEventRecord(ev[3], s));
+        HIP_TRY(launch_collect(A, W, slot, s, h->cus));
         HIP_TRY(launch_resolve(W, slot, s, h->cus));
         if (timing) HIP_TRY(hipEventRecord(ev[4], s));
         HIP_TRY(launch_apply(A, W, slot, transposed, s, h->cus));
@@ -743,6 +743,40 @@ static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const i
     if (st != HWPM_OK) return st;
     S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
     if (stats) *stats = S;
+    return HWPM_OK;
+}
+
+int hwpm_autotune(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
+                  hwpm_options* opt, float* ms_out, void* workspace, size_t workspace_bytes) {
+    static const int32_t kCand[HWPM_TUNE_CANDIDATES][2] = {
+        {1, 4}, {1, 8}, {1, 16}, {1, 32}, {1, 64}, {3, 4}, {3, 8}, {3, 16}, {3, 32}, {4, 4}};
+    if (!h || !opt) return HWPM_EINVAL;
+    int st = check_options(*opt);
+    if (st != HWPM_OK) return st;
+    float best_ms[HWPM_TUNE_CANDIDATES];
+    for (int c = 0; c < HWPM_TUNE_CANDIDATES; ++c) best_ms[c] = 3.0e38f;
+    hwpm_options o = *opt;
+    for (int rep = 0; rep < 2; ++rep) {
+        for (int c = 0; c < HWPM_TUNE_CANDIDATES; ++c) {
+            o.probe = kCand[c][0];
+            o.tile_width = kCand[c][1];
+            o.check_csc = (rep == 0 && c == 0) ? opt->check_csc : 0;  // validate once
+            o.timing = 0;
+            const auto t0 = std::chrono::steady_clock::now();
+            st = hwpm_improve(h, A, mate_in, perm_out, nullptr, &o, nullptr, workspace, workspace_bytes);
+            const float ms =
+                std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (st != HWPM_OK) return st;
+            if (ms < best_ms[c]) best_ms[c] = ms;
+        }
+    }
+    int win = 0;
+    for (int c = 1; c < HWPM_TUNE_CANDIDATES; ++c)
+        if (best_ms[c] < best_ms[win]) win = c;
+    if (ms_out)
+        for (int c = 0; c < HWPM_TUNE_CANDIDATES; ++c) ms_out[c] = best_ms[c];
+    opt->probe = kCand[win][0];
+    opt->tile_width = kCand[win][1];
     return HWPM_OK;
 }
 

@@ -26,6 +26,7 @@ enum SlotWord : int {
     kCand = 0,         // roots with a Step-C winner
     kApplied = 1,      // cycles flipped
     kRoots = 2,        // roots to search in this round (incremental mode)
+    kMedium = 3,       // roots handed to the wave-per-root search this round
     kSlotWords = 4,
 };
 
@@ -81,6 +82,7 @@ struct Work {
     int32_t* flips;     // 4 per flipped cycle: (i, new mate j), (l, new mate c)
     int32_t* dirty;     // n: root must be searched again (incremental mode)
     int32_t* dirty_list;// n: the roots to search next round
+    int32_t* medium;    // n: roots for the wave-per-root search (this round)
     // staging of the bucketed transpose
     int32_t* colof;     // nnz: column of each CSC entry
     int32_t* tp_row;

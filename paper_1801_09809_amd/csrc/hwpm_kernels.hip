@@ -283,16 +283,27 @@ __global__ __launch_bounds__(256) void k_search_short(Csc A, Work W, int32_t lon
     if (lane == 0) publish(W, j, b, slot);
 }
 
+// Hash of a column index into a power-of-two table (Fibonacci hashing).
+__device__ __forceinline__ uint32_t hash_col(int32_t c, uint32_t mask) {
+    return ((uint32_t)c * 0x9E3779B1u >> 12) & mask;
+}
+
 // Long columns: each block takes kLongChunk entries of one column and writes
-// a partial winner; k_merge_long reduces the partials of each column.
-__global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dirty) {
+// a partial winner; k_merge_long reduces the partials of each column.  With
+// the transposed lists and a row list of m_j of at most kLongHashMax entries
+// the block first stores that list in an LDS hash table (column -> list
+// position) and every probe is one lookup; otherwise each probe binary
+// searches row m_j in column m_i.
+constexpr int kLongHashMax = 2048;
+constexpr int kLongHashSlots = 4096;
+
+__global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dirty, int transposed) {
     __shared__ double sg[4];
     __shared__ int32_t si[4], sc[4];
     __shared__ int64_t sk[4], sp[4];
-    const int32_t nl = W.counters[kNumLong];
+    __shared__ int32_t hk[kLongHashSlots], hv[kLongHashSlots];
     const int32_t total = W.counters[kNumChunks];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    (void)nl;
     for (int32_t cid = blockIdx.x; cid < total; cid += gridDim.x) {
         const int32_t a = W.chunk_col[cid];  // long column of this chunk
         const int32_t j = W.long_list[a];
@@ -304,7 +315,46 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
         const int32_t mj = W.mc[j];
         const double wmj = W.wm[j];
         Cand b{0.0, INT32_MAX, -1, -1, -1};
-        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) try_entry(A, W, k, mj, wmj, b);
+        const int32_t rlen = transposed ? W.rlen[j] : INT32_MAX;
+        if (rlen <= kLongHashMax) {
+            const int64_t rs = W.rstart[j];
+            uint32_t size = 256;
+            while ((int32_t)size < 2 * rlen) size <<= 1;
+            const uint32_t mask = size - 1;
+            for (uint32_t x = threadIdx.x; x < size; x += blockDim.x) hk[x] = -1;
+            __syncthreads();
+            for (int32_t x = threadIdx.x; x < rlen; x += blockDim.x) {
+                const int32_t c = W.colidx[rs + x];
+                uint32_t h = hash_col(c, mask);
+                while (atomicCAS(&hk[h], -1, c) != -1) h = (h + 1) & mask;  // keys are distinct
+                hv[h] = x;
+            }
+            __syncthreads();
+            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
+                const int32_t i = A.row_idx[k];
+                if (i <= mj) continue;
+                const int32_t mi = W.mrk[k];
+                uint32_t h = hash_col(mi, mask);
+                int32_t qx = -1;
+                for (;;) {
+                    const int32_t key = hk[h];
+                    if (key == mi) {
+                        qx = hv[h];
+                        break;
+                    }
+                    if (key == -1) break;
+                    h = (h + 1) & mask;
+                }
+                if (qx < 0) continue;
+                const int64_t p = W.cscpos[rs + qx];
+                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
+                if (g > 0.0 && better(g, i, b.g, b.i)) {
+                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+                }
+            }
+        } else {
+            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) try_entry(A, W, k, mj, wmj, b);
+        }
         reduce_best<64>(b);
         if (lane == 0) {
             sg[wave] = b.g; si[wave] = b.i; sc[wave] = b.c; sk[wave] = b.k; sp[wave] = b.p;
@@ -626,6 +676,24 @@ __global__ __launch_bounds__(256) void k_colof_long(Csc A, Work W) {
     }
 }
 
+// Exclusive scan in place of cnt[0..2*64) by the first wave of the block (two
+// values per lane); returns nothing, the caller synchronises.
+__device__ __forceinline__ void wave_scan128(int32_t* cnt) {
+    const int t = threadIdx.x;
+    if (t < 64) {
+        const int32_t a0 = cnt[2 * t], a1 = cnt[2 * t + 1];
+        const int32_t v = a0 + a1;
+        int32_t incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t x = __shfl_up(incl, o, 64);
+            if (t >= o) incl += x;
+        }
+        cnt[2 * t] = incl - v;
+        cnt[2 * t + 1] = incl - v + a0;
+    }
+}
+
 // Pass 1a: per-(bucket, tile) counts, written bucket-major.  The slot of
 // every entry (mrk) is filled beforehand by k_mrk_fill.
 __global__ __launch_bounds__(256) void k_tp_hist(Csc A, const int32_t* __restrict__ mrk, int rb,
@@ -733,7 +801,11 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
     const int t = threadIdx.x;
     if (t < kTpSub) hist[t] = 0;
     __syncthreads();
-    for (int64_t e = e0 + t; e < e1; e += blockDim.x) atomicAdd(&hist[(W.tp_row[e] - r0) >> sb], 1);
+    for (int64_t eb = e0; eb < e1; eb += blockDim.x) {  // uniform trip count
+        const int64_t e = eb + t;
+        const bool ok = e < e1;
+        if (ok) atomicAdd(&hist[(W.tp_row[e] - r0) >> sb], 1);
+    }
     __syncthreads();
     if (t < 64) {  // one wave scans the 64 sub-bucket counts
         const int32_t v = hist[t];
@@ -797,10 +869,17 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
 }
 
 // Pass 3: one block per sub-bucket (at most 128 slots, a few hundred entries
-// on average): count its slots, write their pointers, place every entry.  The
-// block's output window is small, so the scattered placement stays in L2.
+// on average): count its slots, write their pointers, then sort the entries
+// by slot in LDS and write them out contiguously.  A sub-bucket larger than
+// one LDS tile (a heavy row) is placed tile by tile, each tile sorted in LDS
+// and written as one run per slot.
+constexpr int kPlaceTile = 2048;  // entries per LDS tile (256 threads x 8)
+
 __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t nb) {
-    __shared__ int32_t rc[kTpMaxRows / kTpSub];
+    constexpr int NS = kTpMaxRows / kTpSub;  // slots per sub-bucket, at most 128
+    constexpr int U = kPlaceTile / 256;
+    __shared__ int32_t rc[NS], tc[NS], ts[NS];
+    __shared__ int32_t s_key[kPlaceTile], s_col[kPlaceTile], s_pos[kPlaceTile];
     const int32_t g = blockIdx.x;
     const int32_t b = g / kTpSub, sub = g % kTpSub;
     const int sb = rb - 6;
@@ -808,14 +887,30 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     const int64_t s1 = (s0 + ((int64_t)1 << sb) < A.n) ? s0 + ((int64_t)1 << sb) : A.n;
     const int32_t nr = (s1 > s0) ? (int32_t)(s1 - s0) : 0;
     const int64_t e0 = W.tp_sub[g], e1 = W.tp_sub[g + 1];
+    const int64_t len = e1 - e0;
+    const bool one_tile = len <= kPlaceTile;
     const int t = threadIdx.x;
-    for (int x = t; x < nr; x += blockDim.x) rc[x] = 0;
+    if (t < NS) rc[t] = 0;
     __syncthreads();
-    for (int64_t e = e0 + t; e < e1; e += blockDim.x) atomicAdd(&rc[W.tp_row2[e] - s0], 1);
+    int32_t key[U], col[U], pos[U], rk[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) rk[u] = -1;
+    for (int64_t c0 = 0; c0 < len; c0 += kPlaceTile) {  // counts (uniform trip count)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t x = c0 + t + 256 * u;
+            const bool ok = x < len;
+            key[u] = ok ? (int32_t)(W.tp_row2[e0 + x] - s0) : 0;
+            if (one_tile) {
+                col[u] = ok ? W.tp_col2[e0 + x] : 0;
+                pos[u] = ok ? W.tp_pos2[e0 + x] : 0;
+            }
+            if (ok) rk[u] = atomicAdd(&rc[key[u]], 1);
+        }
+    }
     __syncthreads();
-    if (t < 64) {  // one wave scans up to 128 slot counts, two per lane
-        const int32_t a0 = (2 * t < nr) ? rc[2 * t] : 0;
-        const int32_t a1 = (2 * t + 1 < nr) ? rc[2 * t + 1] : 0;
+    if (t < 64) {  // slot pointers; rc becomes the exclusive starts
+        const int32_t a0 = rc[2 * t], a1 = rc[2 * t + 1];
         const int32_t v = a0 + a1;
         int32_t incl = v;
 #pragma unroll
@@ -824,14 +919,14 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
             if (t >= o) incl += x;
         }
         const int32_t ex = incl - v;
+        rc[2 * t] = ex;
+        rc[2 * t + 1] = ex + a0;
         if (2 * t < nr) {
-            rc[2 * t] = ex;
             W.rowptr[s0 + 2 * t] = e0 + ex;
             W.rstart[s0 + 2 * t] = e0 + ex;
             W.rlen[s0 + 2 * t] = a0;
         }
         if (2 * t + 1 < nr) {
-            rc[2 * t + 1] = ex + a0;
             W.rowptr[s0 + 2 * t + 1] = e0 + ex + a0;
             W.rstart[s0 + 2 * t + 1] = e0 + ex + a0;
             W.rlen[s0 + 2 * t + 1] = a1;
@@ -839,10 +934,59 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     }
     if (g == nb * kTpSub - 1 && t == 0) W.rowptr[A.n] = A.nnz;
     __syncthreads();
-    for (int64_t e = e0 + t; e < e1; e += blockDim.x) {
-        const int64_t q = e0 + atomicAdd(&rc[W.tp_row2[e] - s0], 1);
-        W.colidx[q] = W.tp_col2[e];
-        W.cscpos[q] = W.tp_pos2[e];
+    if (one_tile) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (rk[u] >= 0) {
+                const int32_t d = rc[key[u]] + rk[u];
+                s_col[d] = col[u];
+                s_pos[d] = pos[u];
+            }
+        }
+        __syncthreads();
+        for (int32_t x = t; x < (int32_t)len; x += 256) {
+            W.colidx[e0 + x] = s_col[x];
+            W.cscpos[e0 + x] = s_pos[x];
+        }
+        return;
+    }
+    for (int64_t c0 = 0; c0 < len; c0 += kPlaceTile) {
+        const int32_t tl = (int32_t)((len - c0 < kPlaceTile) ? len - c0 : kPlaceTile);
+        if (t < NS) tc[t] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int32_t x = t + 256 * u;
+            const bool ok = x < tl;
+            key[u] = ok ? (int32_t)(W.tp_row2[e0 + c0 + x] - s0) : 0;
+            col[u] = ok ? W.tp_col2[e0 + c0 + x] : 0;
+            pos[u] = ok ? W.tp_pos2[e0 + c0 + x] : 0;
+            rk[u] = ok ? atomicAdd(&tc[key[u]], 1) : -1;
+        }
+        __syncthreads();
+        if (t < NS) ts[t] = tc[t];
+        __syncthreads();
+        wave_scan128(ts);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (rk[u] >= 0) {
+                const int32_t d = ts[key[u]] + rk[u];
+                s_key[d] = key[u];
+                s_col[d] = col[u];
+                s_pos[d] = pos[u];
+            }
+        }
+        __syncthreads();
+        for (int32_t x = t; x < tl; x += 256) {
+            const int32_t k = s_key[x];
+            const int64_t dst = e0 + rc[k] + (x - ts[k]);
+            W.colidx[dst] = s_col[x];
+            W.cscpos[dst] = s_pos[x];
+        }
+        __syncthreads();
+        if (t < NS) rc[t] += tc[t];
+        __syncthreads();
     }
 }
 
@@ -1106,11 +1250,97 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
                 }
             }
         } else {
-            root_generic<T, E>(A, W, lane, j, lo, hi, mj, wmj, rs, rlen, b);
+            // too long for the tile: one wave per root searches it
+            if (lane == 0) W.medium[atomicAdd(&W.counters[slot_word(slot, kMedium)], 1)] = j;
+            return;  // tile-uniform
         }
     }
     reduce_best<T>(b);
     if (lane == 0) publish(W, j, b, slot);
+}
+
+// Steps A-C for the roots a tile cannot hold (a column or a row list longer
+// than T*E): one wave per root.  When the row list of m_j has at most
+// kHashMax entries the wave stores it in an LDS hash table (column -> list
+// position) and every probe m_i is one lookup (the marking trick of Section 4
+// with a hash set for the mark array); longer lists take the binary search of
+// row m_j in column m_i.  The 64 lanes stride over the column.
+constexpr int kHashMax = 512;       // row-list entries a wave hashes
+constexpr int kHashSlots = 1024;    // table size per wave (load factor <= 1/2)
+
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot) {
+    __shared__ int32_t keys[4][kHashSlots];
+    __shared__ int32_t vals[4][kHashSlots];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int32_t* hk = keys[wv];
+    int32_t* hv = vals[wv];
+    const int32_t count = W.counters[slot_word(slot, kMedium)];
+    const int32_t waves = gridDim.x * 4;
+    for (int32_t q = blockIdx.x * 4 + wv; q < count; q += waves) {  // wave-uniform
+        const int32_t j = W.medium[q];
+        const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+        const int32_t mj = W.mc[j];
+        const double wmj = W.wm[j];
+        const int64_t rs = W.rstart[j];
+        const int32_t rlen = W.rlen[j];
+        Cand b{0.0, INT32_MAX, -1, -1, -1};
+        if (rlen <= kHashMax) {
+            uint32_t size = 64;
+            while ((int32_t)size < 2 * rlen) size <<= 1;
+            const uint32_t mask = size - 1;
+            wave_lds_sync();  // the previous root's lookups are done
+            for (uint32_t x = lane; x < size; x += 64) hk[x] = -1;
+            wave_lds_sync();
+            for (int32_t x = lane; x < rlen; x += 64) {
+                const int32_t c = W.colidx[rs + x];
+                uint32_t h = hash_col(c, mask);
+                while (atomicCAS(&hk[h], -1, c) != -1) h = (h + 1) & mask;  // keys are distinct
+                hv[h] = x;
+            }
+            wave_lds_sync();
+            for (int64_t k = lo + lane; k < hi; k += 64) {
+                const int32_t i = A.row_idx[k];
+                if (i <= mj) continue;
+                const int32_t mi = W.mrk[k];
+                uint32_t h = hash_col(mi, mask);
+                int32_t qx = -1;
+                for (;;) {
+                    const int32_t key = hk[h];
+                    if (key == mi) {
+                        qx = hv[h];
+                        break;
+                    }
+                    if (key == -1) break;
+                    h = (h + 1) & mask;
+                }
+                if (qx < 0) continue;
+                const int64_t p = W.cscpos[rs + qx];
+                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
+                if (g > 0.0 && better(g, i, b.g, b.i)) {
+                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+                }
+            }
+        } else {
+            for (int64_t k = lo + lane; k < hi; k += 64) {
+                const int32_t i = A.row_idx[k];
+                if (i <= mj) continue;
+                const int32_t mi = W.mrk[k];
+                const int64_t p = find_row(A.col_ptr, A.row_idx, mi, mj);
+                if (p < 0) continue;
+                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
+                if (g > 0.0 && better(g, i, b.g, b.i)) {
+                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+                }
+            }
+        }
+        reduce_best<64>(b);
+        if (lane == 0) publish(W, j, b, slot);
+    }
 }
 
 // Steps A-C, transposed probe, vector form: a quad of lanes per root; each
@@ -1187,7 +1417,8 @@ __global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_
                 }
             }
         } else {
-            root_generic<T, E>(A, W, lane, j, lo, hi, mj, wmj, rs, rlen, b);
+            if (lane == 0) W.medium[atomicAdd(&W.counters[slot_word(slot, kMedium)], 1)] = j;
+            return;  // tile-uniform
         }
     }
     reduce_best<T>(b);
@@ -1228,10 +1459,11 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
         default: return hipErrorInvalidValue;
     }
 #undef HWPM_SEARCH
+    if (probe >= 3) hipLaunchKernelGGL(k_search_medium, dim3(cus * 8), dim3(256), 0, s, A, W, slot);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !has_long) return e;
     const int only_dirty = (roots && incremental) ? 1 : 0;
-    hipLaunchKernelGGL(k_search_long, dim3(cus * 8), dim3(256), 0, s, A, W, only_dirty);
+    hipLaunchKernelGGL(k_search_long, dim3(cus * 8), dim3(256), 0, s, A, W, only_dirty, probe >= 2 ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_merge_long, dim3(64), dim3(256), 0, s, W, slot, only_dirty);
@@ -1351,6 +1583,7 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.flips = (int32_t*)take(N * 4 * 4 / 2 + 16);
     W.dirty = (int32_t*)take(N * 4);
     W.dirty_list = (int32_t*)take(N * 4);
+    W.medium = (int32_t*)take(N * 4);
     const TpPlan P = tp_plan(n, nnz);
     const size_t tpm = P.ok ? (size_t)(P.nb * P.nseg) : 0;
     const size_t tpz = P.ok ? Z : 0;

@@ -238,7 +238,7 @@ int solve_batch(hwpm_server_s* S, int index, std::vector<Request*>& batch, char*
 }
 
 void worker(hwpm_server_s* S, int index) {
-    hipSetDevice(S->opt.device);
+    (void)hipSetDevice(S->opt.device);
     for (;;) {
         std::vector<Request*> batch;
         size_t off = 0, bytes = 0;
@@ -258,7 +258,7 @@ void worker(hwpm_server_s* S, int index) {
             S->stats.max_running = std::max<int64_t>(S->stats.max_running, S->running);
         }
         const int st = solve_batch(S, index, batch, S->arena_base + off, bytes);
-        if (st != HWPM_OK) hipStreamSynchronize(S->streams[index]);  // nothing may still use the region
+        if (st != HWPM_OK) (void)hipStreamSynchronize(S->streams[index]);  // nothing may still use the region
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->arena->release(off, bytes);
@@ -285,8 +285,8 @@ void free_server(hwpm_server_s* S) {
     for (hwpm_handle h : S->handles)
         if (h) hwpm_destroy(h);
     for (hipStream_t s : S->streams)
-        if (s) hipStreamDestroy(s);
-    if (S->arena_base) hipFree(S->arena_base);
+        if (s) (void)hipStreamDestroy(s);
+    if (S->arena_base) (void)hipFree(S->arena_base);
     delete S;
 }
 
@@ -339,7 +339,7 @@ int hwpm_server_create(hwpm_server* out, const hwpm_server_options* opt_in) {
         st = hwpm_create(&h, opt.device, s);
         if (st == HWPM_OK) S->handles.push_back(h);
     }
-    if (prev >= 0) hipSetDevice(prev);
+    if (prev >= 0) (void)hipSetDevice(prev);
     if (st != HWPM_OK) {
         free_server(S);
         return st;
@@ -359,9 +359,9 @@ int hwpm_server_destroy(hwpm_server s) {
     for (auto& t : s->threads) t.join();
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    hipSetDevice(s->opt.device);
+    (void)hipSetDevice(s->opt.device);
     free_server(s);
-    if (prev >= 0) hipSetDevice(prev);
+    if (prev >= 0) (void)hipSetDevice(prev);
     return HWPM_OK;
 }
 

@@ -28,11 +28,13 @@ HWPM_EDEVICE = -7
 HWPM_EINTERNAL = -8
 HWPM_PENDING = 1
 MAX_ROUND_STATS = 512
+TUNE_CANDIDATES = 10
+TUNE_CONFIGS = ((1, 4), (1, 8), (1, 16), (1, 32), (1, 64), (3, 4), (3, 8), (3, 16), (3, 32), (4, 4))
 
 EXPORTED = (
     "hwpm_default_options", "hwpm_strerror", "hwpm_create", "hwpm_destroy",
     "hwpm_workspace_bytes", "hwpm_check_csc", "hwpm_improve", "hwpm_match",
-    "hwpm_batch_workspace_bytes", "hwpm_improve_batch", "hwpm_match_batch",
+    "hwpm_autotune", "hwpm_batch_workspace_bytes", "hwpm_improve_batch", "hwpm_match_batch",
     "hwpm_server_default_options", "hwpm_server_create", "hwpm_server_destroy",
     "hwpm_submit", "hwpm_poll", "hwpm_server_get_stats",
 )
@@ -199,6 +201,9 @@ def load_library(path: str = LIB_PATH):
         lib.hwpm_improve.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, vp,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(hwpm_options),
                                      ctypes.POINTER(hwpm_stats), vp, ctypes.c_size_t]
+        lib.hwpm_autotune.restype = ctypes.c_int
+        lib.hwpm_autotune.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, vp, ctypes.POINTER(hwpm_options),
+                                      ctypes.POINTER(ctypes.c_float), vp, ctypes.c_size_t]
         lib.hwpm_server_default_options.restype = None
         lib.hwpm_server_default_options.argtypes = [ctypes.POINTER(hwpm_server_options)]
         lib.hwpm_server_create.restype = ctypes.c_int
@@ -291,6 +296,19 @@ def hwpm_match(handle: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: int
         ctypes.byref(stats) if stats is not None else None,
         ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes))
     return st, total.value, stats
+
+
+def hwpm_autotune(handle: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: int, weight_ptr: int,
+                  mate_ptr: int, perm_ptr: int, ws_ptr: int, ws_bytes: int,
+                  options: hwpm_options | None = None):
+    """Returns (status, tuned options, per-candidate best ms list)."""
+    A = _csc(n, nnz, col_ptr_ptr, row_idx_ptr, weight_ptr)
+    opt = options if options is not None else hwpm_default_options()
+    ms = (ctypes.c_float * TUNE_CANDIDATES)()
+    st = load_library().hwpm_autotune(ctypes.c_void_p(handle), ctypes.byref(A), ctypes.c_void_p(mate_ptr),
+                                      ctypes.c_void_p(perm_ptr), ctypes.byref(opt), ms,
+                                      ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes))
+    return st, opt, list(ms)
 
 
 def _csc_array(mats):
@@ -504,6 +522,25 @@ class Solver:
 
     def match_batch(self, mats, perms=None, **kw):
         return self._batch(mats, None, perms, True, **kw)
+
+    def autotune(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
+                 mate_in: torch.Tensor, perm_out: torch.Tensor | None = None, **kw):
+        """Returns (probe, tile_width, {(probe, tile): best ms}, perm_out)."""
+        n = col_ptr.numel() - 1
+        nnz = row_idx.numel()
+        self._check(col_ptr, torch.int64, "col_ptr")
+        self._check(row_idx, torch.int32, "row_idx")
+        self._check(w, torch.float64, "w", nnz)
+        self._check(mate_in, torch.int32, "mate_in", n)
+        if perm_out is None:
+            perm_out = torch.empty(n, dtype=torch.int32, device=self.device)
+        ws = self._workspace(n, nnz)
+        st, opt, ms = hwpm_autotune(self.handle, n, nnz, col_ptr.data_ptr(), row_idx.data_ptr(), w.data_ptr(),
+                                    mate_in.data_ptr(), perm_out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    self.options(**kw))
+        if st != HWPM_OK:
+            raise HwpmError(st, "hwpm_autotune")
+        return opt.probe, opt.tile_width, dict(zip(TUNE_CONFIGS, ms)), perm_out
 
     def improve(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
                 mate_in: torch.Tensor, perm_out: torch.Tensor | None = None, max_rounds: int = 0,

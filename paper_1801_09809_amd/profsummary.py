@@ -3,7 +3,7 @@ folder, and derive the HBM traffic of a kernel from two counter passes.
 
     python -m paper_1801_09809_amd.profsummary trace RESULTS.db --command "..."
     python -m paper_1801_09809_amd.profsummary traffic --fetch FETCH.db --write WRITE.db \
-        --kernel k_search_chunk --copy-bytes N --source csrc/hwpm_kernels.hip --out profiles/traffic.json
+        --kernel k_search_chunk,k_search_medium --name search_stage --copy-bytes N --source csrc/hwpm_kernels.hip --out profiles/traffic.json
 
 Reads only the SQLite files rocprofv3 writes (views `kernels` and
 `counters_collection`).  Counter values are summed over the rows of one
@@ -100,14 +100,22 @@ def _calibrated(db, counter, kernel_key, copy_bytes):
 
 
 def cmd_traffic(args) -> int:
-    kname, f_kib, f_copy, f_fac, nf = _calibrated(args.fetch, "FETCH_SIZE", args.kernel, args.copy_bytes)
-    _, w_kib, w_copy, w_fac, nw = _calibrated(args.write, "WRITE_SIZE", args.kernel, args.copy_bytes)
+    """Traffic of one stage: the kernels named by --kernel (comma-separated
+    substrings), each launched once per stage; their per-dispatch averages add."""
+    keys = [k for k in args.kernel.split(",") if k]
     sha = hashlib.sha256(open(args.source, "rb").read()).hexdigest()[:16]
-    read_b = f_kib * 1024.0 * f_fac
-    write_b = w_kib * 1024.0 * w_fac
-    rec = {"kernel": kname, "kernel_src_sha": sha, "bytes_per_launch": read_b + write_b,
+    kernels = {}
+    read_b = write_b = 0.0
+    f_copy = w_copy = f_fac = w_fac = None
+    for key in keys:
+        kname, f_kib, f_copy, f_fac, nf = _calibrated(args.fetch, "FETCH_SIZE", key, args.copy_bytes)
+        _, w_kib, w_copy, w_fac, nw = _calibrated(args.write, "WRITE_SIZE", key, args.copy_bytes)
+        kernels[kname] = {"fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib,
+                          "dispatches": [nf, nw]}
+        read_b += f_kib * 1024.0 * f_fac
+        write_b += w_kib * 1024.0 * w_fac
+    rec = {"kernels": kernels, "kernel_src_sha": sha, "bytes_per_launch": read_b + write_b,
            "read_bytes_per_launch": read_b, "write_bytes_per_launch": write_b,
-           "fetch_kib_per_dispatch": f_kib, "write_kib_per_dispatch": w_kib, "dispatches": [nf, nw],
            "copy_bytes": args.copy_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
            "fetch_factor": f_fac, "write_factor": w_fac, "command": args.command}
     data = {}
@@ -116,7 +124,7 @@ def cmd_traffic(args) -> int:
             data = json.load(f)
     except (OSError, ValueError):
         pass
-    data[args.kernel] = rec
+    data[args.name] = rec
     with open(args.out, "w") as f:
         json.dump(data, f, indent=1, sort_keys=True)
         f.write("\n")
@@ -134,7 +142,8 @@ def main(argv=None) -> int:
     r = sub.add_parser("traffic")
     r.add_argument("--fetch", required=True, help="database of the FETCH_SIZE pass")
     r.add_argument("--write", required=True, help="database of the WRITE_SIZE pass")
-    r.add_argument("--kernel", required=True, help="substring naming one kernel")
+    r.add_argument("--kernel", required=True, help="comma-separated substrings, one per kernel of the stage")
+    r.add_argument("--name", required=True, help="key of the record in the output file")
     r.add_argument("--copy-bytes", type=int, required=True, help="bytes of each calibration copy")
     r.add_argument("--source", required=True, help="source file of the kernel (its hash is recorded)")
     r.add_argument("--out", required=True)

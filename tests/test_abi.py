@@ -137,6 +137,7 @@ def test_host_argument_checks():
     assert lib.hwpm_improve(ctypes.c_void_p(1), None, None, None, None, None, None, None, 0) == hwpm.HWPM_EINVAL
     assert hwpm.hwpm_check_csc(0, 3, 3, 1, 1, 1, 1, 1 << 20) == hwpm.HWPM_EINVAL
     assert lib.hwpm_create(None, 0, None) == hwpm.HWPM_EINVAL
+    assert lib.hwpm_autotune(None, None, None, None, None, None, None, 0) == hwpm.HWPM_EINVAL
     assert hwpm.hwpm_destroy(0) == hwpm.HWPM_OK
 
 

@@ -517,3 +517,22 @@ def test_batch_rejects_bad_member(solver):
     assert e.value.status == hwpm.HWPM_EBADMATCH
     perms, totals, items, _ = solver.improve_batch([], [])
     assert perms == [] and totals == []
+
+
+# ---------------------------------------------------------------------------
+# launch-configuration tuner: picks a configuration, never changes a result
+
+@pytest.mark.parametrize("which", ["random", "rmat"])
+def test_autotune_keeps_the_result(solver, which):
+    from paper_1801_09809_amd import hwpm
+    wl = small_random(30000, 12, 77) if which == "random" else rmat(12, 16, 1012, 2012, 3012, name="rmat_s12")
+    ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
+    dev = solver.device
+    print(f"[gpu] autotune {wl.name} n={wl.n} nnz={wl.nnz}", flush=True)
+    probe, tile, ms, perm = solver.autotune(_dev(wl.col_ptr, dev), _dev(wl.row_idx, dev), _dev(wl.w, dev),
+                                            _dev(wl.planted, dev))
+    assert (probe, tile) in hwpm.TUNE_CONFIGS
+    assert all(0.0 < v < 1e30 for v in ms.values())
+    assert min(ms, key=ms.get) == (probe, tile)
+    assert np.array_equal(perm.cpu().numpy(), ref.perm)
+    assert_same(wl, gpu_improve(solver, wl, probe=probe, tile_width=tile), ref)

@@ -9,7 +9,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhwpm.so")
-SOURCES = ["hwpm_api.hip", "hwpm_kernels.hip", "hwpm_mcm.hip", "hwpm_batch.hip", "hwpm_server.cpp"]
+SOURCES = ["hwpm_api.hip", "hwpm_kernels.hip", "hwpm_search.hip", "hwpm_mcm.hip", "hwpm_batch.hip",
+           "hwpm_server.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

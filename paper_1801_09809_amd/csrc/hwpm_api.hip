@@ -16,7 +16,9 @@ struct hwpm_handle_s {
     hipStream_t stream;
     int cus;
     int32_t* host;        // pinned host buffer for counter / result readback
-    hipEvent_t ev[8];
+    // 0-7: stage events; 8 + 4*b .. 8 + 4*b + 3: the stages of the b-th
+    // round of a batch of queued rounds
+    hipEvent_t ev[8 + 4 * kSlots];
 };
 
 namespace {
@@ -24,6 +26,12 @@ namespace {
 constexpr int kDefaultTile = 4;
 constexpr int kDefaultProbe = 3;
 constexpr int32_t kLongThreshold = 256;   // longer columns use the split search
+// int32 index of the 8-byte scalar readback slot in the pinned host buffer
+// (after the two ring slots of per-round words)
+constexpr int kHostScalar = 64;
+// int32 index of the per-round statistics (3 x kMaxRoundStats words)
+constexpr int kHostRounds = 256;
+constexpr size_t kHostBytes = (kHostRounds + 3 * kMaxRoundStats) * sizeof(int32_t);
 constexpr int64_t kMaxNnz = (int64_t)1 << 40;
 
 struct DeviceGuard {
@@ -102,7 +110,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     HIP_TRY(launch_init_match(A, W, mate_in, kLongThreshold, s));
     HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[1], s));
     HIP_TRY(hipMemcpyAsync(h->host, W.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h->host + 8, &W.result[1], sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[1], sizeof(double), hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(hipStreamSynchronize(s));
     if (timing) S.ms_setup = elapsed(ev[0], ev[1]);
@@ -111,7 +119,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     const int32_t n_long = h->host[kNumLong];
     if (n_long > 0) HIP_TRY(launch_long_chunks(W, A, s));
     S.long_columns = n_long;
-    memcpy(&S.init_weight, h->host + 8, sizeof(double));
+    memcpy(&S.init_weight, h->host + kHostScalar, sizeof(double));
     if (transposed) {
         if (timing) HIP_TRY(hipEventRecord(ev[0], s));
         if (incremental) HIP_TRY(hipMemsetAsync(W.dirty, 0, (size_t)n * sizeof(int32_t), s));
@@ -125,56 +133,68 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
 
     // 3. rounds.  In incremental mode the first round searches every root and
     // later rounds only the roots the previous flips touched (the others keep
-    // their Step-C records, which cannot have changed).
-    int32_t round = 0;
-    int32_t nroots = n;
+    // their Step-C records, which cannot have changed).  Rounds are queued in
+    // batches of 1, 1, 2, 4, 8, 8, ... with no host round trip inside a
+    // batch: the round that flips nothing raises a device flag and every
+    // round kernel queued after it returns at once.
+    int32_t round = 0;  // rounds queued
+    int32_t batch = 1;
+    int32_t done = 0, rounds_run = 0;
     for (;;) {
-        if (opt.max_rounds > 0 && round >= opt.max_rounds) {
-            S.hit_round_cap = 1;
-            break;
+        int32_t nb = batch;
+        if (opt.max_rounds > 0 && opt.max_rounds - round < nb) nb = opt.max_rounds - round;
+        if (nb <= 0) break;  // the round cap
+        for (int32_t b = 0; b < nb; ++b) {
+            const int32_t r = round + b;
+            const int slot = r % kSlots;
+            const bool listed = incremental && r > 0;
+            hipEvent_t* e = ev + 8 + 4 * b;
+            if (timing) HIP_TRY(hipEventRecord(e[0], s));
+            HIP_TRY(launch_search(A, W, tile, kLongThreshold, slot, n_long > 0, probe, listed, incremental, s,
+                                  h->cus));
+            if (timing) HIP_TRY(hipEventRecord(e[1], s));
+            HIP_TRY(launch_collect(A, W, slot, s, h->cus));
+            HIP_TRY(launch_resolve(W, slot, s, h->cus));
+            if (timing) HIP_TRY(hipEventRecord(e[2], s));
+            HIP_TRY(launch_apply(A, W, slot, transposed, s, h->cus));
+            if (transposed) HIP_TRY(launch_mrk_update(W, slot, incremental, s, h->cus));
+            if (BP) HIP_TRY(launch_item_rounds(*BP, W.counters + kDone, s));
+            if (timing) HIP_TRY(hipEventRecord(e[3], s));
+            HIP_TRY(launch_round_end(W, slot, r, listed, n, s));
         }
-        const int slot = round % kSlots;
-        const bool listed = incremental && round > 0;
-        if (timing) HIP_TRY(hipEventRecord(ev[2], s));
-        if (!listed || nroots > 0)
-            HIP_TRY(launch_search(A, W, tile, kLongThreshold, slot, n_long > 0, probe,
-                                  listed ? W.dirty_list : nullptr, nroots, incremental, s, h->cus));
-        if (timing) HIP_TRY(hipEventRecord(ev[3], s));
-        HIP_TRY(launch_collect(A, W, slot, s, h->cus));
-        HIP_TRY(launch_resolve(W, slot, s, h->cus));
-        if (timing) HIP_TRY(hipEventRecord(ev[4], s));
-        HIP_TRY(launch_apply(A, W, slot, transposed, s, h->cus));
-        if (transposed) HIP_TRY(launch_mrk_update(W, slot, incremental, s, h->cus));
-        if (BP) HIP_TRY(launch_item_rounds(*BP, s));
-        if (timing) HIP_TRY(hipEventRecord(ev[5], s));
-        HIP_TRY(hipMemcpyAsync(h->host, W.counters + slot_word(slot, 0), kSlotWords * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(h->host + kSlotWords, W.counters + slot_word((slot + 1) % kSlots, 0),
-                               kSlotWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        round += nb;
+        HIP_TRY(hipMemcpyAsync(h->host, W.counters + kDone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        const int32_t n_cand = h->host[kCand], n_applied = h->host[kApplied];
-        if (round < HWPM_MAX_ROUND_STATS) {
-            S.round_candidates[round] = n_cand;
-            S.round_applied[round] = n_applied;
-            S.round_roots[round] = nroots;
-        }
-        nroots = incremental ? h->host[kSlotWords + kRoots] : n;
+        done = h->host[0];
+        rounds_run = h->host[1];
         if (timing) {
-            const float ms = elapsed(ev[2], ev[3]);
-            S.ms_search += ms;
-            if (round == 0) S.ms_search_first = ms;
-            if (round < HWPM_MAX_ROUND_STATS) S.round_ms_search[round] = ms;
-            S.ms_resolve += elapsed(ev[3], ev[4]);
-            S.ms_apply += elapsed(ev[4], ev[5]);
+            for (int32_t b = 0; b < nb; ++b) {
+                const int32_t r = round - nb + b;
+                if (r >= rounds_run) break;
+                hipEvent_t* e = ev + 8 + 4 * b;
+                const float ms = elapsed(e[0], e[1]);
+                S.ms_search += ms;
+                if (r == 0) S.ms_search_first = ms;
+                if (r < HWPM_MAX_ROUND_STATS) S.round_ms_search[r] = ms;
+                S.ms_resolve += elapsed(e[1], e[2]);
+                S.ms_apply += elapsed(e[2], e[3]);
+            }
         }
-        S.cycles_applied += n_applied;
-        ++round;
         // A round with candidates always flips at least one cycle (the
         // candidate whose other column has the largest matched row).
-        if (n_cand > 0 && n_applied == 0) return HWPM_EINTERNAL;
-        if (n_applied == 0) break;
+        if (done == 2) return HWPM_EINTERNAL;
+        if (done) break;
+        batch = round < 2 ? 1 : (2 * batch < kSlots ? 2 * batch : kSlots);
     }
-    S.rounds = round;
+    if (!done) S.hit_round_cap = 1;
+    S.rounds = done ? rounds_run : round;
+    static_assert(kMaxRoundStats == HWPM_MAX_ROUND_STATS, "round statistics sizes");
+    const int32_t n_stats = S.rounds < kMaxRoundStats ? S.rounds : kMaxRoundStats;
+    // per-round statistics and the cycle count, into the pinned buffer
+    if (n_stats > 0)
+        HIP_TRY(hipMemcpyAsync(h->host + kHostRounds, W.round_stats, 3 * kMaxRoundStats * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->host + kHostScalar + 2, W.counters + kCycles, 8, hipMemcpyDeviceToHost, s));
 
     // 4. outputs
     if (timing) HIP_TRY(hipEventRecord(ev[6], s));
@@ -184,12 +204,20 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
         HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_total, s, h->cus));
         HIP_TRY(launch_unpack(*BP, W.mc, s, h->cus));
     }
-    HIP_TRY(hipMemcpyAsync(h->host + 8, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[7], s));
     HIP_TRY(hipStreamSynchronize(s));
     if (timing) S.ms_final = elapsed(ev[6], ev[7]);
+    unsigned long long cycles = 0;
+    memcpy(&cycles, h->host + kHostScalar + 2, sizeof(cycles));
+    S.cycles_applied = (int64_t)cycles;
+    if (n_stats > 0) {
+        memcpy(S.round_candidates, h->host + kHostRounds, (size_t)n_stats * sizeof(int32_t));
+        memcpy(S.round_applied, h->host + kHostRounds + kMaxRoundStats, (size_t)n_stats * sizeof(int32_t));
+        memcpy(S.round_roots, h->host + kHostRounds + 2 * kMaxRoundStats, (size_t)n_stats * sizeof(int32_t));
+    }
     double total;
-    memcpy(&total, h->host + 8, sizeof(double));
+    memcpy(&total, h->host + kHostScalar, sizeof(double));
     S.final_weight = total;
     *total_out = total;
     return HWPM_OK;
@@ -234,16 +262,17 @@ int run_initial_matching(hwpm_handle h, const Csc& A, const Work& W, const Mcm& 
     HIP_TRY(hipMemcpyAsync(host, W.counters + kNumLong, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     const bool has_long = host[0] > 0;
-    int32_t rounds = 0;
-    for (;;) {
-        HIP_TRY(hipMemsetAsync(M.counters, 0, kMcmWords * sizeof(int32_t), s));
-        HIP_TRY(launch_greedy_round(A, M, W, heavy, kLongThreshold, has_long, s, h->cus));
-        HIP_TRY(hipMemcpyAsync(host, M.counters, kMcmWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // greedy rounds, queued in batches of 1, 2, 4, 8, 8, ... (the round that
+    // finds no proposal ends the loop on the device)
+    HIP_TRY(hipMemsetAsync(M.counters, 0, kMcmWords * sizeof(int32_t), s));
+    for (int32_t batch = 1;; batch = batch < 8 ? 2 * batch : 8) {
+        for (int32_t b = 0; b < batch; ++b)
+            HIP_TRY(launch_greedy_round(A, M, W, heavy, kLongThreshold, has_long, s, h->cus));
+        HIP_TRY(hipMemcpyAsync(host, M.counters + kMcmDone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        ++rounds;
-        if (host[kMcmProposals] == 0) break;
+        if (host[0]) break;
     }
-    S->greedy_rounds = rounds;
+    S->greedy_rounds = host[1];
     if (timing) {
         HIP_TRY(hipEventRecord(ev[1], s));
         HIP_TRY(hipEventSynchronize(ev[1]));
@@ -264,21 +293,20 @@ int run_initial_matching(hwpm_handle h, const Csc& A, const Work& W, const Mcm& 
         }
         if (unmatched == 0) break;
         ++phases;
-        int32_t nf = unmatched;
-        int32_t* cur = M.front_a;
-        int32_t* nxt = M.front_b;
-        while (nf > 0) {
-            HIP_TRY(launch_bfs_level(A, M, cur, nf, nxt, heavy, s, h->cus));
-            HIP_TRY(hipMemcpyAsync(host, M.counters, kMcmWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        // levels, queued in batches of 1, 2, 4, 8, 8, ...: a level with an
+        // empty frontier does nothing, so the phase's levels end on the device
+        for (int32_t level = 0, batch = 1;; batch = batch < 8 ? 2 * batch : 8) {
+            for (int32_t b = 0; b < batch; ++b, ++level)
+                HIP_TRY(launch_bfs_level(A, M, level, heavy, s, h->cus));
+            const int nw = (level & 1) ? kMcmNext : kMcmFrontier;  // next level's frontier
+            HIP_TRY(hipMemcpyAsync(host, M.counters + nw, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            ++levels;
-            nf = host[kMcmNext];
-            HIP_TRY(hipMemsetAsync(M.counters + kMcmNext, 0, 2 * sizeof(int32_t), s));  // next, level
-            int32_t* t = cur; cur = nxt; nxt = t;
+            if (host[0] == 0) break;
         }
         HIP_TRY(launch_bfs_augment(A, M, s, h->cus));
         HIP_TRY(hipMemcpyAsync(host, M.counters, kMcmWords * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        levels += host[kMcmLevels];
         if (host[kMcmAugmented] == 0) break;  // no augmenting path: maximum reached
     }
     S->mcm_phases = phases;
@@ -496,9 +524,13 @@ int hwpm_create(hwpm_handle* out, int device, void* stream) {
     if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         h->cus <= 0)
         h->cus = 256;
+    constexpr int kEvents = (int)(sizeof(h->ev) / sizeof(h->ev[0]));
     int ne = 0;
-    bool ok = hipHostMalloc((void**)&h->host, 4096, hipHostMallocDefault) == hipSuccess;
-    for (; ok && ne < 8; ++ne) ok = hipEventCreate(&h->ev[ne]) == hipSuccess;
+    bool ok = hipHostMalloc((void**)&h->host, kHostBytes, hipHostMallocDefault) == hipSuccess;
+    while (ok && ne < kEvents) {
+        ok = hipEventCreate(&h->ev[ne]) == hipSuccess;
+        if (ok) ++ne;
+    }
     if (!ok) {
         for (int e = 0; e < ne; ++e) (void)hipEventDestroy(h->ev[e]);
         if (h->host) (void)hipHostFree(h->host);
@@ -513,7 +545,7 @@ int hwpm_destroy(hwpm_handle h) {
     if (!h) return HWPM_OK;
     DeviceGuard g(h->device);
     (void)hipStreamSynchronize(h->stream);
-    for (int e = 0; e < 8; ++e) (void)hipEventDestroy(h->ev[e]);
+    for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     (void)hipHostFree(h->host);
     delete h;
     return HWPM_OK;

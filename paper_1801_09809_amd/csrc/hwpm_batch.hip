@@ -143,7 +143,9 @@ __global__ __launch_bounds__(1024) void k_seg_tree_final(const BatchItem* __rest
 }
 
 // Rounds in which each block flipped at least one cycle.
-__global__ void k_item_rounds(int32_t* __restrict__ flag, int32_t* __restrict__ rounds, int32_t count) {
+__global__ void k_item_rounds(int32_t* __restrict__ flag, int32_t* __restrict__ rounds, int32_t count,
+                              const int32_t* __restrict__ done) {
+    if (*done) return;  // a round queued after the loop ended
     for (int32_t b = blockIdx.x * blockDim.x + threadIdx.x; b < count; b += gridDim.x * blockDim.x) {
         if (flag[b]) {
             ++rounds[b];
@@ -186,8 +188,8 @@ hipError_t launch_seg_tree(const BatchPlan& P, const double* x, double* out, hip
     return hipGetLastError();
 }
 
-hipError_t launch_item_rounds(const BatchPlan& P, hipStream_t s) {
-    hipLaunchKernelGGL(k_item_rounds, dim3(64), dim3(256), 0, s, P.item_flag, P.item_rounds, P.count);
+hipError_t launch_item_rounds(const BatchPlan& P, const int32_t* done, hipStream_t s) {
+    hipLaunchKernelGGL(k_item_rounds, dim3(64), dim3(256), 0, s, P.item_flag, P.item_rounds, P.count, done);
     return hipGetLastError();
 }
 

@@ -1,0 +1,117 @@
+// Device helpers shared by the search and round kernels: the closing-edge
+// probe by binary search, the Step-C winner record and its order, the
+// cross-lane winner reduction and the column hash of the LDS tables.
+#pragma once
+
+#include "hwpm_internal.h"
+
+namespace hwpm {
+
+// Round kernels launched after the round that ended the loop do nothing.
+__device__ __forceinline__ bool round_over(const Work& W) { return W.counters[kDone] != 0; }
+
+__device__ __forceinline__ unsigned long long gain_bits(double g) {
+    // g > 0 (finite or +inf): the IEEE bit pattern orders like the value.
+    return (unsigned long long)__double_as_longlong(g);
+}
+
+// Position of row r in column c, or -1 when the entry {r, c} is absent.
+// Binary search down to a window of at most 9 positions, then an unrolled
+// scan whose loads are independent (one memory round trip for short columns).
+__device__ __forceinline__ int64_t find_row(const int64_t* __restrict__ col_ptr,
+                                            const int32_t* __restrict__ row_idx, int32_t c,
+                                            int32_t r) {
+    int64_t lo = col_ptr[c];
+    const int64_t end = col_ptr[c + 1];
+    int64_t len = end - lo;
+    while (len > 8) {
+        const int64_t half = len >> 1;
+        if (row_idx[lo + half] < r) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    // the first row >= r lies in [lo, lo + len]
+    int64_t hit = -1;
+#pragma unroll
+    for (int q = 0; q <= 8; ++q) {
+        const int64_t pos = lo + q;
+        if (q <= len && pos < end && row_idx[pos] == r) hit = pos;
+    }
+    return hit;
+}
+
+// Winner order of Step C: larger gain first, then smaller row.
+struct Cand {
+    double g;     // 0.0 = none (candidates have g > 0)
+    int32_t i;    // INT32_MAX = none
+    int32_t c;
+    int64_t k;
+    int64_t p;
+};
+
+__device__ __forceinline__ bool better(double g1, int32_t i1, double g2, int32_t i2) {
+    return g1 > g2 || (g1 == g2 && i1 < i2);
+}
+
+// Record the Step-C winner of root j (or its absence).
+__device__ __forceinline__ void publish(const Work& W, int32_t j, const Cand& b, int slot) {
+    (void)slot;
+    if (b.i == INT32_MAX) {
+        W.best_i[j] = -1;
+        return;
+    }
+    W.best_i[j] = b.i;
+    W.best_g[j] = b.g;
+    W.best_c[j] = b.c;
+    W.best_k[j] = b.k;
+    W.best_p[j] = b.p;
+}
+
+// One entry {i, j} of root column j (mate row mj, matched weight wmj):
+// Steps A and B for the cycle (i, j, m_j, m_i), folded into the running best.
+__device__ __forceinline__ void try_entry(const Csc& A, const Work& W, int64_t k, int32_t mj,
+                                          double wmj, Cand& b) {
+    const int32_t i = A.row_idx[k];
+    if (i <= mj) return;                    // rows i > m_j only
+    const int32_t mi = W.mr[i];
+    const int64_t p = find_row(A.col_ptr, A.row_idx, mi, mj);  // edge {m_j, m_i}
+    if (p < 0) return;
+    const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
+    if (g > 0.0 && better(g, i, b.g, b.i)) {
+        b.g = g;
+        b.i = i;
+        b.c = mi;
+        b.k = k;
+        b.p = p;
+    }
+}
+
+template <int WIDTH>
+__device__ __forceinline__ void reduce_best(Cand& b) {
+#pragma unroll
+    for (int off = WIDTH / 2; off >= 1; off >>= 1) {
+        const double og = __shfl_xor(b.g, off, WIDTH);
+        const int32_t oi = __shfl_xor(b.i, off, WIDTH);
+        const int32_t oc = __shfl_xor(b.c, off, WIDTH);
+        const int64_t ok = __shfl_xor(b.k, off, WIDTH);
+        const int64_t op = __shfl_xor(b.p, off, WIDTH);
+        if (better(og, oi, b.g, b.i)) {
+            b.g = og;
+            b.i = oi;
+            b.c = oc;
+            b.k = ok;
+            b.p = op;
+        }
+    }
+}
+
+// Hash of a column index into a power-of-two table (Fibonacci hashing).
+__device__ __forceinline__ uint32_t hash_col(int32_t c, uint32_t mask) {
+    return ((uint32_t)c * 0x9E3779B1u >> 12) & mask;
+}
+
+
+}  // namespace hwpm

@@ -10,6 +10,7 @@ constexpr int32_t kNoRoot = 0x7fffffff;   // empty Step-D slot
 constexpr int kSlots = 8;                  // ring of per-round counter pairs
 constexpr int kLongChunk = 1024;           // entries per block in the long-column search
 constexpr int kTreeBlock = 2048;           // leaves summed by one tree-sum block
+constexpr int kMaxRoundStats = 512;        // rounds with per-round statistics
 
 // Counter words (int32) at the start of the counter area.
 enum CounterWord : int {
@@ -17,8 +18,12 @@ enum CounterWord : int {
     kErrMatch = 1,     // matching validation flags
     kNumLong = 2,      // number of long columns
     kNumChunks = 3,    // chunks of the long-column search
+    kDone = 4,         // 0 while rounds run; 1 after a round that flipped nothing;
+                       // 2 if that round had candidates (a broken invariant)
+    kRoundsRun = 5,    // search passes run so far
+    kCycles = 6,       // u64 in words 6-7: cycles flipped in all rounds
     kRoundBase = 8,    // per-round words, kSlotWords per slot of the ring
-    kCounterWords = 64,
+    kCounterWords = 128,
 };
 
 // Per-round words of one ring slot.
@@ -27,7 +32,8 @@ enum SlotWord : int {
     kApplied = 1,      // cycles flipped
     kRoots = 2,        // roots to search in this round (incremental mode)
     kMedium = 3,       // roots handed to the wave-per-root search this round
-    kSlotWords = 4,
+    kHeavy = 4,        // flipped rows whose mate columns are refreshed by the whole grid
+    kSlotWords = 8,
 };
 
 __host__ __device__ inline int slot_word(int slot, int w) { return kRoundBase + kSlotWords * slot + w; }
@@ -83,6 +89,8 @@ struct Work {
     int32_t* dirty;     // n: root must be searched again (incremental mode)
     int32_t* dirty_list;// n: the roots to search next round
     int32_t* medium;    // n: roots for the wave-per-root search (this round)
+    int32_t* heavy;     // n: new mate columns of the flipped rows with long lists (this round)
+    int32_t* round_stats; // 3 x kMaxRoundStats: candidates, flips, roots searched
     // staging of the bucketed transpose
     int32_t* colof;     // nnz: column of each CSC entry
     int32_t* tp_row;
@@ -148,6 +156,9 @@ enum McmWord : int {
     kMcmNext = 3,
     kMcmLevelLen = 4,
     kMcmAugmented = 5,
+    kMcmDone = 8,         // greedy: a round found no proposal (later rounds do nothing)
+    kMcmRounds = 9,       // greedy: proposal rounds run
+    kMcmLevels = 10,      // BFS: levels with a nonempty frontier
     kMcmWords = 16,
 };
 
@@ -180,8 +191,9 @@ hipError_t launch_init_match(const Csc& A, const Work& W, const int32_t* mate_in
                              int32_t long_threshold, hipStream_t s);
 hipError_t launch_long_chunks(const Work& W, const Csc& A, hipStream_t s);
 hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t long_threshold,
-                         int slot, bool has_long, int probe, const int32_t* roots, int32_t nroots,
-                         bool incremental, hipStream_t s, int cus);
+                         int slot, bool has_long, int probe, bool listed, bool incremental, hipStream_t s,
+                         int cus);
+hipError_t launch_round_end(const Work& W, int slot, int round, bool listed, int32_t n, hipStream_t s);
 hipError_t launch_collect(const Csc& A, const Work& W, int slot, hipStream_t s, int cus);
 hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
                             hipStream_t s, int cus);
@@ -195,13 +207,12 @@ hipError_t launch_mcm_init(const Csc& A, const Mcm& M, const Work& W, int32_t lo
 hipError_t launch_greedy_round(const Csc& A, const Mcm& M, const Work& W, int heavy,
                                int32_t long_threshold, bool has_long, hipStream_t s, int cus);
 hipError_t launch_bfs_roots(const Csc& A, const Mcm& M, hipStream_t s, int cus);
-hipError_t launch_bfs_level(const Csc& A, const Mcm& M, const int32_t* fr, int32_t nf,
-                            int32_t* next, int heavy, hipStream_t s, int cus);
+hipError_t launch_bfs_level(const Csc& A, const Mcm& M, int level, int heavy, hipStream_t s, int cus);
 hipError_t launch_bfs_augment(const Csc& A, const Mcm& M, hipStream_t s, int cus);
 hipError_t launch_pack(const BatchPlan& P, bool with_mates, hipStream_t s, int cus);
 hipError_t launch_unpack(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus);
 hipError_t launch_seg_tree(const BatchPlan& P, const double* x, double* out, hipStream_t s, int cus);
-hipError_t launch_item_rounds(const BatchPlan& P, hipStream_t s);
+hipError_t launch_item_rounds(const BatchPlan& P, const int32_t* done, hipStream_t s);
 hipError_t launch_item_unmatched(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus);
 
 }  // namespace hwpm

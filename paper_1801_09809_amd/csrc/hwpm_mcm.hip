@@ -64,8 +64,25 @@ hipError_t launch_mcm_init(const Csc& A, const Mcm& M, const Work& W, int32_t lo
 
 // Every unmatched column proposes to its best unmatched row; pass 1 of the
 // rows' choice (largest weight key) is taken at once.
+// Greedy rounds are queued several at a time: a round that finds no
+// proposal raises kMcmDone and every greedy kernel queued after it returns.
+__global__ void k_greedy_begin(Mcm M) {
+    if (M.counters[kMcmDone]) return;
+    if (threadIdx.x == 0) {
+        M.counters[kMcmProposals] = 0;
+        M.counters[kMcmListLen] = 0;
+    }
+}
+
+__global__ void k_greedy_end(Mcm M) {
+    if (M.counters[kMcmDone]) return;
+    M.counters[kMcmRounds] += 1;
+    if (M.counters[kMcmProposals] == 0) M.counters[kMcmDone] = 1;
+}
+
 template <int T>
 __global__ __launch_bounds__(256) void k_greedy_propose(Csc A, Mcm M, int heavy, int32_t long_threshold) {
+    if (M.counters[kMcmDone]) return;
     const int lane = threadIdx.x & (T - 1);
     const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
     if (tile >= A.n) return;
@@ -103,6 +120,7 @@ __global__ __launch_bounds__(256) void k_greedy_propose(Csc A, Mcm M, int heavy,
 __global__ __launch_bounds__(256) void k_greedy_propose_long(Csc A, Mcm M, const Work W, int heavy) {
     __shared__ double sw[4];
     __shared__ int32_t sr[4];
+    if (M.counters[kMcmDone]) return;
     const int32_t nl = W.counters[kNumLong];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int32_t q = blockIdx.x; q < nl; q += gridDim.x) {
@@ -143,6 +161,7 @@ __global__ __launch_bounds__(256) void k_greedy_propose_long(Csc A, Mcm M, const
 
 // Pass 2 of the rows' choice: smallest column among the max-key proposers.
 __global__ void k_greedy_accept(Mcm M, int heavy) {
+    if (M.counters[kMcmDone]) return;
     const int32_t np = M.counters[kMcmListLen];
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < np; t += gridDim.x * blockDim.x) {
         const int32_t j = M.list[t];
@@ -154,6 +173,7 @@ __global__ void k_greedy_accept(Mcm M, int heavy) {
 // Match the accepted pairs; the winner clears its row's slots (losers only
 // compare the slot with their own index).
 __global__ void k_greedy_match(Mcm M) {
+    if (M.counters[kMcmDone]) return;
     const int32_t np = M.counters[kMcmListLen];
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < np; t += gridDim.x * blockDim.x) {
         const int32_t j = M.list[t];
@@ -187,11 +207,30 @@ __global__ void k_bfs_roots(Csc A, Mcm M) {
     }
 }
 
+// Levels are queued several at a time; the frontier of level L lives in
+// front_a / front_b by the parity of L, its length in the counter word of the
+// same parity (kMcmFrontier / kMcmNext).  A level whose frontier is empty does
+// nothing but mark the next frontier empty, so levels queued after the last
+// one are no-ops.  Level start: clear the level list and the next frontier's
+// length, count the level.
+__global__ void k_bfs_level_begin(Mcm M, int level) {
+    const int cur = (level & 1) ? kMcmNext : kMcmFrontier;
+    const int nxt = (level & 1) ? kMcmFrontier : kMcmNext;
+    if (M.counters[cur] == 0) {  // past the last level: keep the emptiness going
+        M.counters[nxt] = 0;
+        return;
+    }
+    M.counters[kMcmLevelLen] = 0;
+    M.counters[nxt] = 0;
+    M.counters[kMcmLevels] += 1;
+}
+
 // Level step, pass 1: every row adjacent to a frontier column and not visited
 // in an earlier level is touched (listed once) and its best parent key raised.
 template <int T>
 __global__ __launch_bounds__(256) void k_bfs_expand(Csc A, Mcm M, const int32_t* __restrict__ fr,
-                                                    int32_t nf, int heavy) {
+                                                    const int32_t* __restrict__ nfp, int heavy) {
+    const int32_t nf = *nfp;
     const int lane = threadIdx.x & (T - 1);
     const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
     const int64_t ntiles = ((int64_t)gridDim.x * blockDim.x) / T;
@@ -218,7 +257,8 @@ __global__ __launch_bounds__(256) void k_bfs_expand(Csc A, Mcm M, const int32_t*
 // Level step, pass 2: parent = smallest frontier column among the heaviest.
 template <int T>
 __global__ __launch_bounds__(256) void k_bfs_parent(Csc A, Mcm M, const int32_t* __restrict__ fr,
-                                                    int32_t nf, int heavy) {
+                                                    const int32_t* __restrict__ nfp, int heavy) {
+    const int32_t nf = *nfp;
     const int lane = threadIdx.x & (T - 1);
     const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
     const int64_t ntiles = ((int64_t)gridDim.x * blockDim.x) / T;
@@ -235,7 +275,8 @@ __global__ __launch_bounds__(256) void k_bfs_parent(Csc A, Mcm M, const int32_t*
 
 // Level step, pass 3: the level's rows join their parents' trees; unmatched
 // rows are endpoints (each tree keeps its smallest).
-__global__ void k_bfs_join(Mcm M) {
+__global__ void k_bfs_join(Mcm M, const int32_t* __restrict__ nf) {
+    if (*nf == 0) return;  // a level queued after the last one
     const int32_t nl = M.counters[kMcmLevelLen];
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += gridDim.x * blockDim.x) {
         const int32_t r = M.level[t];
@@ -247,7 +288,9 @@ __global__ void k_bfs_join(Mcm M) {
 
 // Level step, pass 4: the mates of the level's matched rows in trees that are
 // still growing form the next frontier.
-__global__ void k_bfs_next(Mcm M, int32_t* __restrict__ next) {
+__global__ void k_bfs_next(Mcm M, int32_t* __restrict__ next, int32_t* __restrict__ next_len,
+                           const int32_t* __restrict__ nf) {
+    if (*nf == 0) return;
     const int32_t nl = M.counters[kMcmLevelLen];
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += gridDim.x * blockDim.x) {
         const int32_t r = M.level[t];
@@ -256,7 +299,7 @@ __global__ void k_bfs_next(Mcm M, int32_t* __restrict__ next) {
         const int32_t tr = M.tree_row[r];
         if (M.end_row[tr] != kNoRoot) continue;
         M.tree_col[m] = tr;
-        const int32_t q = atomicAdd(&M.counters[kMcmNext], 1);
+        const int32_t q = atomicAdd(next_len, 1);
         next[q] = m;
     }
 }
@@ -284,10 +327,12 @@ __global__ void k_bfs_augment(Csc A, Mcm M) {
 hipError_t launch_greedy_round(const Csc& A, const Mcm& M, const Work& W, int heavy,
                                int32_t long_threshold, bool has_long, hipStream_t s, int cus) {
     const unsigned blocks = (unsigned)(((int64_t)A.n * 16 + 255) / 256);
+    hipLaunchKernelGGL(k_greedy_begin, dim3(1), dim3(64), 0, s, M);
     hipLaunchKernelGGL(k_greedy_propose<16>, dim3(blocks), dim3(256), 0, s, A, M, heavy, long_threshold);
     if (has_long) hipLaunchKernelGGL(k_greedy_propose_long, dim3(cus * 2), dim3(256), 0, s, A, M, W, heavy);
     hipLaunchKernelGGL(k_greedy_accept, dim3(cus * 2), dim3(256), 0, s, M, heavy);
     hipLaunchKernelGGL(k_greedy_match, dim3(cus * 2), dim3(256), 0, s, M);
+    hipLaunchKernelGGL(k_greedy_end, dim3(1), dim3(1), 0, s, M);
     return hipGetLastError();
 }
 
@@ -296,14 +341,18 @@ hipError_t launch_bfs_roots(const Csc& A, const Mcm& M, hipStream_t s, int cus) 
     return hipGetLastError();
 }
 
-hipError_t launch_bfs_level(const Csc& A, const Mcm& M, const int32_t* fr, int32_t nf,
-                            int32_t* next, int heavy, hipStream_t s, int cus) {
-    const int64_t want = ((int64_t)nf * 64 + 255) / 256;
+hipError_t launch_bfs_level(const Csc& A, const Mcm& M, int level, int heavy, hipStream_t s, int cus) {
+    const int32_t* fr = (level & 1) ? M.front_b : M.front_a;
+    int32_t* next = (level & 1) ? M.front_a : M.front_b;
+    const int32_t* nf = M.counters + ((level & 1) ? kMcmNext : kMcmFrontier);
+    int32_t* next_len = M.counters + ((level & 1) ? kMcmFrontier : kMcmNext);
+    const int64_t want = ((int64_t)A.n * 64 + 255) / 256;
     const unsigned blocks = (unsigned)(want < cus * 16 ? (want > 0 ? want : 1) : cus * 16);
+    hipLaunchKernelGGL(k_bfs_level_begin, dim3(1), dim3(1), 0, s, M, level);
     hipLaunchKernelGGL(k_bfs_expand<64>, dim3(blocks), dim3(256), 0, s, A, M, fr, nf, heavy);
     hipLaunchKernelGGL(k_bfs_parent<64>, dim3(blocks), dim3(256), 0, s, A, M, fr, nf, heavy);
-    hipLaunchKernelGGL(k_bfs_join, dim3(cus * 2), dim3(256), 0, s, M);
-    hipLaunchKernelGGL(k_bfs_next, dim3(cus * 2), dim3(256), 0, s, M, next);
+    hipLaunchKernelGGL(k_bfs_join, dim3(cus * 2), dim3(256), 0, s, M, nf);
+    hipLaunchKernelGGL(k_bfs_next, dim3(cus * 2), dim3(256), 0, s, M, next, next_len, nf);
     return hipGetLastError();
 }
 

@@ -43,6 +43,55 @@ __device__ __forceinline__ int64_t find_row(const int64_t* __restrict__ col_ptr,
     return hit;
 }
 
+// Four probes at once: out[q] = position of row r[q] in column c[q], or -1
+// (also for c[q] < 0).  The same search as find_row, with the four searches
+// advanced in lockstep so that their loads are independent: one memory round
+// trip per step for all four instead of one per step for each.
+__device__ __forceinline__ void find_row_x4(const int64_t* __restrict__ col_ptr,
+                                            const int32_t* __restrict__ row_idx, const int32_t* c,
+                                            const int32_t* r, int64_t* out) {
+    int64_t lo[4], end[4], len[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        lo[q] = (c[q] >= 0) ? col_ptr[c[q]] : 0;
+        end[q] = (c[q] >= 0) ? col_ptr[c[q] + 1] : 0;
+        len[q] = end[q] - lo[q];
+    }
+    for (;;) {
+        bool any = false;
+        int32_t v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const bool go = len[q] > 8;
+            any |= go;
+            v[q] = go ? row_idx[lo[q] + (len[q] >> 1)] : 0;
+        }
+        if (!any) break;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (len[q] > 8) {
+                const int64_t half = len[q] >> 1;
+                if (v[q] < r[q]) {
+                    lo[q] += half + 1;
+                    len[q] -= half + 1;
+                } else {
+                    len[q] = half;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        int64_t hit = -1;
+#pragma unroll
+        for (int x = 0; x <= 8; ++x) {
+            const int64_t pos = lo[q] + x;
+            if (x <= len[q] && pos < end[q] && row_idx[pos] == r[q]) hit = pos;
+        }
+        out[q] = hit;
+    }
+}
+
 // Winner order of Step C: larger gain first, then smaller row.
 struct Cand {
     double g;     // 0.0 = none (candidates have g > 0)

@@ -98,7 +98,29 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
                 }
             }
         } else {
-            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) try_entry(A, W, k, mj, wmj, b);
+            // four entries per thread, their binary searches in lockstep
+            const int32_t step = blockDim.x;
+            for (int64_t k0 = lo + threadIdx.x; k0 < hi; k0 += 4 * (int64_t)step) {
+                int32_t iq[4], cq[4], rq[4];
+                int64_t pq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t k = k0 + (int64_t)q * step;
+                    iq[q] = (k < hi) ? A.row_idx[k] : -1;
+                    cq[q] = (k < hi && iq[q] > mj) ? (transposed ? W.mrk[k] : W.mr[iq[q]]) : -1;
+                    rq[q] = mj;
+                }
+                find_row_x4(A.col_ptr, A.row_idx, cq, rq, pq);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (pq[q] < 0) continue;
+                    const int64_t k = k0 + (int64_t)q * step;
+                    const double g = (A.w[k] + A.w[pq[q]]) - (W.wm[cq[q]] + wmj);
+                    if (g > 0.0 && better(g, iq[q], b.g, b.i)) {
+                        b.g = g; b.i = iq[q]; b.c = cq[q]; b.k = k; b.p = pq[q];
+                    }
+                }
+            }
         }
         reduce_best<64>(b);
         if (lane == 0) {
@@ -350,15 +372,26 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot) 
                 }
             }
         } else {
-            for (int64_t k = lo + lane; k < hi; k += 64) {
-                const int32_t i = A.row_idx[k];
-                if (i <= mj) continue;
-                const int32_t mi = W.mrk[k];
-                const int64_t p = find_row(A.col_ptr, A.row_idx, mi, mj);
-                if (p < 0) continue;
-                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
-                if (g > 0.0 && better(g, i, b.g, b.i)) {
-                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+            // four entries per lane, their binary searches in lockstep
+            for (int64_t k0 = lo + lane; k0 < hi; k0 += 4 * 64) {
+                int32_t iq[4], cq[4], rq[4];
+                int64_t pq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t k = k0 + 64 * q;
+                    iq[q] = (k < hi) ? A.row_idx[k] : -1;
+                    cq[q] = (k < hi && iq[q] > mj) ? W.mrk[k] : -1;
+                    rq[q] = mj;
+                }
+                find_row_x4(A.col_ptr, A.row_idx, cq, rq, pq);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (pq[q] < 0) continue;
+                    const int64_t k = k0 + 64 * q;
+                    const double g = (A.w[k] + A.w[pq[q]]) - (W.wm[cq[q]] + wmj);
+                    if (g > 0.0 && better(g, iq[q], b.g, b.i)) {
+                        b.g = g; b.i = iq[q]; b.c = cq[q]; b.k = k; b.p = pq[q];
+                    }
                 }
             }
         }

@@ -88,8 +88,9 @@ typedef struct {
     int32_t check_csc;
     /* 1 = time every stage with HIP events into hwpm_stats (ms_*). */
     int32_t timing;
-    /* Lanes per column in the cycle-search kernel: 0 = default, else one of
-     * 4, 8, 16, 32, 64.  Results do not depend on it. */
+    /* Lanes per column in the cycle-search kernel: 0 = default (4; 8 with
+     * probe 3 when the matrix has more than 20 entries per column on
+     * average), else one of 4, 8, 16, 32, 64.  Results do not depend on it. */
     int32_t tile_width;
     /* How the closing edge {m_j, m_i} is probed (results do not depend on it):
      * 0 = default; 1 = binary search of row m_j in column m_i; 2 = build the
@@ -283,20 +284,23 @@ int hwpm_match_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, int32_t
 /* ---- serving --------------------------------------------------------------
  * A request loop for callers that produce a stream of independent matrices
  * (e.g. a sparse direct solver that pivots every matrix it factorises).
- * hwpm_submit takes a HOST CSC, validates it on the host and copies it into
- * a FIFO queue.  Each worker owns a handle on its own HIP stream: whenever
- * it is idle it admits, in arrival order, as many queued requests as fit into
- * the free part of the server's device arena (their inputs, results and the
- * batch workspace -- admission by HBM footprint), solves them as one
+ * hwpm_submit queues a HOST CSC by reference.  Each worker owns a handle on
+ * its own HIP stream: whenever it is idle it admits, in arrival order, as
+ * many queued requests as fit into the largest free extent of the server's
+ * device arena (their inputs, results and the batch workspace -- admission by
+ * HBM footprint), copies them in, validates and solves them as one
  * hwpm_match_batch and hands back the results.  Requests that arrive while
  * batches run join the next batch that has room (continuous batching), and
  * the batches of different workers overlap on the device.  Results equal
  * those of hwpm_match on each matrix alone.
  *
- * Ownership: the server allocates its arena (arena_bytes of device memory),
- * one stream and handle per worker and the host copies of queued requests;
+ * Ownership: the caller's host arrays of a request must stay valid and
+ * unchanged until hwpm_poll has returned its result (or until
+ * hwpm_server_destroy has returned).  The server allocates its arena
+ * (arena_bytes of device memory) and one stream and handle per worker;
  * hwpm_server_destroy finishes the queued requests and frees everything.
- * hwpm_submit, hwpm_poll and hwpm_server_get_stats are thread-safe. */
+ * hwpm_submit, hwpm_poll and hwpm_server_get_stats are thread-safe; none of
+ * them may run concurrently with hwpm_server_destroy. */
 typedef struct hwpm_server_s* hwpm_server;
 
 typedef struct {
@@ -329,8 +333,9 @@ typedef struct {
 } hwpm_server_stats;
 
 /* Defaults: device 0, 2 workers, max_batch 64, 8 GiB arena, solve options
- * from hwpm_default_options with check_csc = 0 (requests are validated on
- * the host at submission). */
+ * from hwpm_default_options (check_csc = 1: every batch is validated on the
+ * device; a batch with a malformed member is solved member by member, so
+ * only that member reports HWPM_EBADCSC). */
 void hwpm_server_default_options(hwpm_server_options* opt);
 
 /* Start a server (opt may be NULL for the defaults).  Errors: HWPM_EINVAL
@@ -341,16 +346,18 @@ int hwpm_server_create(hwpm_server* out, const hwpm_server_options* opt);
  * not yet polled are discarded. */
 int hwpm_server_destroy(hwpm_server s);
 
-/* Queue one matrix; A holds HOST pointers and is copied before the call
- * returns.  *ticket identifies the request in hwpm_poll.  Errors: HWPM_EINVAL,
- * HWPM_ETOOBIG, HWPM_EBADCSC (the same checks as hwpm_check_csc, on the
- * host); a rejected matrix is not queued. */
+/* Queue one matrix; A holds HOST pointers, kept by reference (see
+ * ownership above).  *ticket identifies the request in hwpm_poll.  Errors:
+ * HWPM_EINVAL (null pointer, negative size), HWPM_ETOOBIG, HWPM_EBADCSC
+ * (col_ptr[0] != 0 or col_ptr[n] != nnz); a rejected matrix is not queued.
+ * Every other check of hwpm_check_csc runs on the device and its failure is
+ * the request's status in hwpm_poll. */
 int hwpm_submit(hwpm_server s, const hwpm_csc* A, uint64_t* ticket);
 
 /* Result of a request.  wait = 0 returns HWPM_PENDING at once if it has not
  * finished; wait = 1 blocks until it has.  On completion returns the
- * request's status (HWPM_OK, HWPM_ESINGULAR, HWPM_ETOOBIG when it cannot fit
- * the arena even alone, or the batch's error), writes perm_host (host
+ * request's status (HWPM_OK, HWPM_ESINGULAR, HWPM_EBADCSC, HWPM_ETOOBIG when
+ * it cannot fit the arena even alone, or the batch's error), writes perm_host (host
  * int32[n], nullable) and *total (nullable) when HWPM_OK, fills *info
  * (nullable) and forgets the ticket.  An unknown ticket gives HWPM_EINVAL. */
 int hwpm_poll(hwpm_server s, uint64_t ticket, int32_t wait, int32_t* perm_host, double* total,

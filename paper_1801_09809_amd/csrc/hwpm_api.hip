@@ -97,8 +97,11 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     hipStream_t s = h->stream;
     const bool timing = opt.timing != 0;
     hipEvent_t* ev = h->ev;
-    const int tile = opt.tile_width ? opt.tile_width : kDefaultTile;
     int probe = opt.probe ? opt.probe : kDefaultProbe;
+    // default tile: 4 lanes per root for short columns, 8 from about 20
+    // entries per column on (the chunked kernel then holds 32 per tile either way)
+    const int tile = opt.tile_width ? opt.tile_width
+                                    : (probe == 3 && A.nnz > 20 * (int64_t)A.n ? 8 : kDefaultTile);
     // the vector kernel reads row_idx in aligned 16-byte windows
     if (probe == 4 && ((uintptr_t)A.row_idx & 15)) probe = 3;
     const bool transposed = probe >= 2;

@@ -38,6 +38,22 @@ enum SlotWord : int {
 
 __host__ __device__ inline int slot_word(int slot, int w) { return kRoundBase + kSlotWords * slot + w; }
 
+// Append to a device list whose length is *counter: every active lane of the
+// wave with want set gets its own slot (returned; -1 for the others), and
+// the wave adds to the counter once.  Many lanes appending at once would
+// otherwise queue on the one counter address.  All active lanes of the wave
+// must call it together.
+__device__ __forceinline__ int32_t wave_append(int32_t* counter, bool want) {
+    const unsigned long long m = __ballot(want);
+    if (m == 0ull) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll(m) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (int32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    return want ? base + (int32_t)__popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
 // Matrix in CSC form (device pointers).
 struct Csc {
     int32_t n;

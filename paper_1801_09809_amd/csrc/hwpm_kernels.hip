@@ -173,13 +173,15 @@ __global__ void k_collect(Csc A, Work W, int slot) {
     for (int64_t jj = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; jj < A.n;
          jj += (int64_t)gridDim.x * blockDim.x) {
         const int32_t j = (int32_t)jj;
-        if (W.best_i[j] < 0) continue;
-        const int32_t c = W.best_c[j];
-        const unsigned long long gb = gain_bits(W.best_g[j]);
-        if (__hip_atomic_load(&W.dgain[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gb)
-            atomicMax(&W.dgain[c], gb);
-        const int32_t q = atomicAdd(&W.counters[slot_word(slot, kCand)], 1);
-        W.cand[q] = j;
+        const bool has = W.best_i[j] >= 0;
+        if (has) {
+            const int32_t c = W.best_c[j];
+            const unsigned long long gb = gain_bits(W.best_g[j]);
+            if (__hip_atomic_load(&W.dgain[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gb)
+                atomicMax(&W.dgain[c], gb);
+        }
+        const int32_t q = wave_append(&W.counters[slot_word(slot, kCand)], has);
+        if (has) W.cand[q] = j;
     }
 }
 
@@ -220,8 +222,11 @@ __global__ void k_apply(Csc A, Work W, int slot, int transposed) {
         const int32_t c = W.best_c[j];
         W.dgain[j] = 0ull;
         W.droot[j] = kNoRoot;
-        if (W.best_i[c] >= 0) continue;
-        if (__hip_atomic_load(&W.droot[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != j) continue;
+        const bool won = W.best_i[c] < 0 &&
+                         __hip_atomic_load(&W.droot[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == j;
+        // the two rows whose mate changed, for the per-entry mate columns
+        const int32_t q = wave_append(&W.counters[slot_word(slot, kApplied)], won);
+        if (!won) continue;
         const int32_t i = W.best_i[j];
         const int32_t l = W.mc[j];
         W.mc[j] = i;
@@ -244,8 +249,6 @@ __global__ void k_apply(Csc A, Work W, int slot, int transposed) {
             W.item_flag[blk] = 1;
             atomicAdd(&W.item_cycles[blk], 1ull);
         }
-        // the two rows whose mate changed, for the per-entry mate columns
-        const int32_t q = atomicAdd(&W.counters[slot_word(slot, kApplied)], 1);
         W.flips[4 * (int64_t)q + 0] = i;
         W.flips[4 * (int64_t)q + 1] = j;
         W.flips[4 * (int64_t)q + 2] = l;
@@ -824,11 +827,10 @@ __device__ __forceinline__ void refresh_entry(const Work& W, int64_t x, int32_t 
     W.mrk[W.cscpos[x]] = m;
     if (incremental) {
         const int32_t c = W.colidx[x];
-        if (__hip_atomic_load(&W.dirty[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-            atomicExch(&W.dirty[c], 1) == 0) {
-            const int32_t q = atomicAdd(&W.counters[slot_word(next, kRoots)], 1);
-            W.dirty_list[q] = c;
-        }
+        const bool first = __hip_atomic_load(&W.dirty[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+                           atomicExch(&W.dirty[c], 1) == 0;
+        const int32_t q = wave_append(&W.counters[slot_word(next, kRoots)], first);
+        if (first) W.dirty_list[q] = c;
     }
 }
 

@@ -77,7 +77,7 @@ __global__ void k_greedy_begin(Mcm M) {
 __global__ void k_greedy_end(Mcm M) {
     if (M.counters[kMcmDone]) return;
     M.counters[kMcmRounds] += 1;
-    if (M.counters[kMcmProposals] == 0) M.counters[kMcmDone] = 1;
+    if (M.counters[kMcmListLen] == 0) M.counters[kMcmDone] = 1;  // no proposal
 }
 
 template <int T>
@@ -104,13 +104,13 @@ __global__ __launch_bounds__(256) void k_greedy_propose(Csc A, Mcm M, int heavy,
         const int32_t orr = __shfl_xor(br, off, T);
         if (g_better(heavy, ow, orr, bw, br)) { bw = ow; br = orr; }
     }
+    const bool propose = lane == 0 && br != INT32_MAX;
+    const int32_t q = wave_append(&M.counters[kMcmListLen], propose);
     if (lane == 0) {
         M.prop_row[j] = br == INT32_MAX ? -1 : br;
-        if (br != INT32_MAX) {
+        if (propose) {
             M.prop_w[j] = bw;
             if (heavy) atomicMax(&M.rkey[br], wkey(bw));
-            atomicAdd(&M.counters[kMcmProposals], 1);
-            const int32_t q = atomicAdd(&M.counters[kMcmListLen], 1);
             M.list[q] = j;
         }
     }
@@ -150,7 +150,6 @@ __global__ __launch_bounds__(256) void k_greedy_propose_long(Csc A, Mcm M, const
             if (br != INT32_MAX) {
                 M.prop_w[j] = bw;
                 if (heavy) atomicMax(&M.rkey[br], wkey(bw));
-                atomicAdd(&M.counters[kMcmProposals], 1);
                 const int32_t s = atomicAdd(&M.counters[kMcmListLen], 1);
                 M.list[s] = j;
             }
@@ -199,9 +198,10 @@ __global__ void k_bfs_roots(Csc A, Mcm M) {
         M.end_row[j] = kNoRoot;
         M.pkey[j] = 0ull;
         M.touched[j] = 0;
-        if (M.mc[j] < 0) {
+        const bool root = M.mc[j] < 0;
+        const int32_t q = wave_append(&M.counters[kMcmFrontier], root);
+        if (root) {
             M.tree_col[j] = j;
-            const int32_t q = atomicAdd(&M.counters[kMcmFrontier], 1);
             M.front_a[q] = j;
         }
     }
@@ -245,11 +245,10 @@ __global__ __launch_bounds__(256) void k_bfs_expand(Csc A, Mcm M, const int32_t*
                 if (__hip_atomic_load(&M.pkey[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < key)
                     atomicMax(&M.pkey[r], key);
             }
-            if (__hip_atomic_load(&M.touched[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
-                atomicExch(&M.touched[r], 1) == 0) {
-                const int32_t q = atomicAdd(&M.counters[kMcmLevelLen], 1);
-                M.level[q] = r;
-            }
+            const bool first = __hip_atomic_load(&M.touched[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
+                               atomicExch(&M.touched[r], 1) == 0;
+            const int32_t q = wave_append(&M.counters[kMcmLevelLen], first);
+            if (first) M.level[q] = r;
         }
     }
 }
@@ -295,11 +294,11 @@ __global__ void k_bfs_next(Mcm M, int32_t* __restrict__ next, int32_t* __restric
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += gridDim.x * blockDim.x) {
         const int32_t r = M.level[t];
         const int32_t m = M.mr[r];
-        if (m < 0) continue;
         const int32_t tr = M.tree_row[r];
-        if (M.end_row[tr] != kNoRoot) continue;
+        const bool grow = m >= 0 && M.end_row[tr] == kNoRoot;
+        const int32_t q = wave_append(next_len, grow);
+        if (!grow) continue;
         M.tree_col[m] = tr;
-        const int32_t q = atomicAdd(next_len, 1);
         next[q] = m;
     }
 }

@@ -1,18 +1,18 @@
 // Serving form: a request loop with continuous batching over hwpm_match_batch.
 //
-// hwpm_submit validates a host CSC and copies it into a FIFO queue.  Each
-// worker thread owns a handle on its own HIP stream; whenever it is idle it
-// takes, in arrival order, as many queued requests as fit into the largest
-// free extent of the device arena (their inputs and results plus the batch
-// workspace: admission by HBM footprint), copies them in, solves them as one
-// block-diagonal batch and hands the results back.  Requests that arrive
-// while batches run are admitted by the next idle worker as soon as there is
-// room, and the batches of different workers overlap on the device.
+// hwpm_submit queues a host CSC (by reference: the caller keeps the arrays
+// until the result is polled).  Each worker thread owns a handle on its own
+// HIP stream; whenever it is idle it takes, in arrival order, as many queued
+// requests as fit into the largest free extent of the device arena (their
+// inputs and results plus the batch workspace: admission by HBM footprint),
+// copies them in, validates and solves them as one block-diagonal batch and
+// hands the results back.  Requests that arrive while batches run are
+// admitted by the next idle worker as soon as there is room, and the batches
+// of different workers overlap on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <chrono>
-#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -40,9 +40,9 @@ struct Request {
     uint64_t ticket = 0;
     int32_t n = 0;
     int64_t nnz = 0;
-    std::vector<int64_t> col_ptr;
-    std::vector<int32_t> row_idx;
-    std::vector<double> w;
+    const int64_t* col_ptr = nullptr;  // the caller's host arrays
+    const int32_t* row_idx = nullptr;
+    const double* w = nullptr;
     size_t input_bytes = 0;  // arena bytes for its arrays and its result
     Clock::time_point t_submit, t_admit, t_done;
     bool done = false;
@@ -99,24 +99,6 @@ class Arena {
     std::map<size_t, size_t> free_;  // offset -> length, no two adjacent
     size_t in_use_ = 0, peak_ = 0;
 };
-
-// The checks of hwpm_check_csc, on the host.
-int host_check(const hwpm_csc* A) {
-    if (A->n < 0 || A->nnz < 0 || !A->col_ptr || (A->nnz > 0 && (!A->row_idx || !A->weight)))
-        return HWPM_EINVAL;
-    if (A->n >= INT32_MAX || A->nnz >= ((int64_t)1 << 40)) return HWPM_ETOOBIG;
-    if (A->col_ptr[0] != 0 || A->col_ptr[A->n] != A->nnz) return HWPM_EBADCSC;
-    for (int32_t j = 0; j < A->n; ++j) {
-        const int64_t a = A->col_ptr[j], b = A->col_ptr[j + 1];
-        if (b < a || a < 0 || b > A->nnz) return HWPM_EBADCSC;
-        for (int64_t k = a; k < b; ++k) {
-            const int32_t r = A->row_idx[k];
-            if (r < 0 || r >= A->n || (k > a && r <= A->row_idx[k - 1]) || !std::isfinite(A->weight[k]))
-                return HWPM_EBADCSC;
-        }
-    }
-    return HWPM_OK;
-}
 
 }  // namespace
 
@@ -204,12 +186,11 @@ int solve_batch(hwpm_server_s* S, int index, std::vector<Request*>& batch, char*
         at += align_up((size_t)r->nnz * 8);
         perms[i] = (int32_t*)(base + at);
         at += align_up((size_t)r->n * 4);
-        if (hipMemcpyAsync(cp, r->col_ptr.data(), (size_t)(r->n + 1) * 8, hipMemcpyHostToDevice, stream) !=
-            hipSuccess)
+        if (hipMemcpyAsync(cp, r->col_ptr, (size_t)(r->n + 1) * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
             return HWPM_EDEVICE;
         if (r->nnz > 0 &&
-            (hipMemcpyAsync(ri, r->row_idx.data(), (size_t)r->nnz * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-             hipMemcpyAsync(w, r->w.data(), (size_t)r->nnz * 8, hipMemcpyHostToDevice, stream) != hipSuccess))
+            (hipMemcpyAsync(ri, r->row_idx, (size_t)r->nnz * 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+             hipMemcpyAsync(w, r->w, (size_t)r->nnz * 8, hipMemcpyHostToDevice, stream) != hipSuccess))
             return HWPM_EDEVICE;
         mats[i].n = r->n;
         mats[i].nnz = r->nnz;
@@ -219,8 +200,32 @@ int solve_batch(hwpm_server_s* S, int index, std::vector<Request*>& batch, char*
     }
     std::vector<double> totals(batch.size());
     std::vector<hwpm_item_stats> items(batch.size());
-    const int st = hwpm_match_batch(S->handles[index], (int32_t)batch.size(), mats.data(), perms.data(),
-                                    totals.data(), &S->opt.solve, items.data(), nullptr, base + at, bytes - at);
+    hwpm_handle h = S->handles[index];
+    int st = hwpm_match_batch(h, (int32_t)batch.size(), mats.data(), perms.data(), totals.data(), &S->opt.solve,
+                              items.data(), nullptr, base + at, bytes - at);
+    if (st == HWPM_EBADCSC && batch.size() > 1) {
+        // a malformed member fails the whole batch: solve the members alone so
+        // that only the malformed ones report it
+        for (size_t i = 0; i < batch.size(); ++i) {
+            hwpm_stats one;
+            const int si = hwpm_match(h, &mats[i], perms[i], &totals[i], &S->opt.solve, &one, base + at, bytes - at);
+            memset(&items[i], 0, sizeof(items[i]));
+            items[i].status = si;
+            if (si == HWPM_OK) {
+                items[i].rounds = one.rounds;
+                items[i].hit_round_cap = one.hit_round_cap;
+                items[i].cycles_applied = one.cycles_applied;
+                items[i].init_weight = one.init_weight;
+                items[i].final_weight = one.final_weight;
+            } else if (si != HWPM_ESINGULAR && si != HWPM_EBADCSC) {
+                return si;
+            }
+        }
+        st = HWPM_OK;
+    } else if (st == HWPM_EBADCSC) {
+        items[0].status = HWPM_EBADCSC;
+        st = HWPM_OK;
+    }
     if (st != HWPM_OK) return st;
     for (size_t i = 0; i < batch.size(); ++i) {
         Request* r = batch[i];
@@ -270,9 +275,6 @@ void worker(hwpm_server_s* S, int index) {
                 r->worker = index;
                 r->t_done = now;
                 r->done = true;
-                std::vector<int64_t>().swap(r->col_ptr);
-                std::vector<int32_t>().swap(r->row_idx);
-                std::vector<double>().swap(r->w);
                 ++S->stats.completed;
             }
         }
@@ -301,8 +303,7 @@ void hwpm_server_default_options(hwpm_server_options* opt) {
     opt->workers = 2;
     opt->max_batch = 64;
     opt->arena_bytes = (size_t)8 << 30;
-    hwpm_default_options(&opt->solve);
-    opt->solve.check_csc = 0;
+    hwpm_default_options(&opt->solve);  // check_csc = 1: requests are validated on the device
 }
 
 int hwpm_server_create(hwpm_server* out, const hwpm_server_options* opt_in) {
@@ -367,15 +368,17 @@ int hwpm_server_destroy(hwpm_server s) {
 
 int hwpm_submit(hwpm_server s, const hwpm_csc* A, uint64_t* ticket) {
     if (!s || !A || !ticket) return HWPM_EINVAL;
-    const int st = host_check(A);
-    if (st != HWPM_OK) return st;
+    if (A->n < 0 || A->nnz < 0 || !A->col_ptr || (A->nnz > 0 && (!A->row_idx || !A->weight)))
+        return HWPM_EINVAL;
+    if (A->n >= INT32_MAX || A->nnz >= ((int64_t)1 << 40)) return HWPM_ETOOBIG;
+    if (A->col_ptr[0] != 0 || A->col_ptr[A->n] != A->nnz) return HWPM_EBADCSC;  // the rest on the device
     auto r = std::make_unique<Request>();
     r->t_submit = Clock::now();
     r->n = A->n;
     r->nnz = A->nnz;
-    r->col_ptr.assign(A->col_ptr, A->col_ptr + (size_t)A->n + 1);
-    r->row_idx.assign(A->row_idx, A->row_idx + A->nnz);
-    r->w.assign(A->weight, A->weight + A->nnz);
+    r->col_ptr = A->col_ptr;
+    r->row_idx = A->row_idx;
+    r->w = A->weight;
     r->input_bytes = align_up((size_t)(A->n + 1) * 8) + align_up((size_t)A->nnz * 4) +
                      align_up((size_t)A->nnz * 8) + align_up((size_t)A->n * 4);
     {

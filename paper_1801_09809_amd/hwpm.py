@@ -566,7 +566,8 @@ class Solver:
 
 
 class Server:
-    """Request loop over host matrices (numpy arrays): submit, then poll."""
+    """Request loop over host matrices (numpy arrays): submit, then poll.  The
+    arrays of a request are kept alive here until its result is polled."""
 
     def __init__(self, device: int = 0, workers: int = 2, max_batch: int = 64,
                  arena_bytes: int = 8 << 30, **solve_kw):
@@ -578,15 +579,16 @@ class Server:
         opt.max_batch = int(max_batch)
         opt.arena_bytes = int(arena_bytes)
         if solve_kw:
-            solve_kw.setdefault("check_csc", False)
             opt.solve = Solver.options(**solve_kw)
         self.server = hwpm_server_create(opt)
         self._n = {}
+        self._keep = {}  # the host arrays of each queued request, until polled
 
     def close(self):
         if self.server:
             hwpm_server_destroy(self.server)
             self.server = 0
+            self._keep.clear()
 
     def __enter__(self):
         return self
@@ -612,6 +614,7 @@ class Server:
         if st != HWPM_OK:
             raise HwpmError(st, "hwpm_submit")
         self._n[ticket] = n
+        self._keep[ticket] = (cp, ri, ww)  # the server reads them until the result is polled
         return ticket
 
     def poll(self, ticket: int, wait: bool = True):
@@ -623,6 +626,7 @@ class Server:
         if st == HWPM_PENDING:
             return None
         del self._n[ticket]
+        self._keep.pop(ticket, None)
         return st, (perm[:n] if st == HWPM_OK else None), total, info.as_dict()
 
     def stats(self) -> dict:

@@ -117,7 +117,7 @@ def cmd_traffic(args) -> int:
     rec = {"kernels": kernels, "kernel_src_sha": sha, "bytes_per_launch": read_b + write_b,
            "read_bytes_per_launch": read_b, "write_bytes_per_launch": write_b,
            "copy_bytes": args.copy_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
-           "fetch_factor": f_fac, "write_factor": w_fac, "command": args.command}
+           "fetch_factor": f_fac, "write_factor": w_fac, "workload": args.workload, "command": args.command}
     data = {}
     try:
         with open(args.out) as f:
@@ -147,6 +147,7 @@ def main(argv=None) -> int:
     r.add_argument("--copy-bytes", type=int, required=True, help="bytes of each calibration copy")
     r.add_argument("--source", required=True, help="source file of the kernel (its hash is recorded)")
     r.add_argument("--out", required=True)
+    r.add_argument("--workload", required=True, help="name of the workload the passes ran on")
     r.add_argument("--command", default="")
     args = ap.parse_args(argv)
     return cmd_trace(args) if args.cmd == "trace" else cmd_traffic(args)

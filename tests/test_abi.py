@@ -87,7 +87,7 @@ def test_server_host_argument_checks():
     lib = hwpm.load_library()
     assert lib.hwpm_server_create(None, None) == hwpm.HWPM_EINVAL
     o = hwpm.hwpm_server_default_options()
-    assert (o.workers, o.max_batch, o.arena_bytes, o.solve.check_csc) == (2, 64, 8 << 30, 0)
+    assert (o.workers, o.max_batch, o.arena_bytes, o.solve.check_csc) == (2, 64, 8 << 30, 1)
     s = ctypes.c_void_p()
     for field, bad in (("workers", 0), ("workers", 17), ("max_batch", 0), ("arena_bytes", 1000)):
         ob = hwpm.hwpm_server_default_options()

@@ -117,9 +117,11 @@ def test_admission_by_footprint():
     assert stats["arena_peak"] <= arena
 
 
-def test_submit_rejects_bad_matrix_and_poll_semantics():
+def test_malformed_requests_fail_alone_and_poll_semantics():
+    """Malformed matrices are reported by their own poll (validated on the
+    device); the well-formed requests batched with them are unaffected."""
     hwpm = _need_gpu()
-    good = small_random(500, 4, 5)
+    good = [small_random(500, 4, 5), small_random(300, 3, 8), stencil27(6, 6, 6, 1, 2)]
     bad = small_random(400, 4, 6)
     ri = bad.row_idx.copy()
     ri[3] = 400  # row out of range
@@ -129,12 +131,23 @@ def test_submit_rejects_bad_matrix_and_poll_semantics():
     unsorted[k], unsorted[k + 1] = unsorted[k + 1], unsorted[k]
     wnan = bad.w.copy()
     wnan[7] = np.nan
-    with hwpm.Server(workers=1) as srv:
-        for r, w in ((ri, bad.w), (unsorted, bad.w), (bad.row_idx, wnan)):
-            with pytest.raises(hwpm.HwpmError) as e:
-                srv.submit(bad.col_ptr, r, w)
-            assert e.value.status == hwpm.HWPM_EBADCSC
-        t = srv.submit(good.col_ptr, good.row_idx, good.w)
+    cp_bad = bad.col_ptr.copy()
+    cp_bad[-1] -= 1  # col_ptr[n] != nnz: refused at submission
+    with hwpm.Server(workers=1, max_batch=64) as srv:
+        with pytest.raises(hwpm.HwpmError) as e:
+            srv.submit(cp_bad, bad.row_idx, bad.w)
+        assert e.value.status == hwpm.HWPM_EBADCSC
+        tickets = []
+        for g, (r, w) in zip(good, ((ri, bad.w), (unsorted, bad.w), (bad.row_idx, wnan))):
+            tickets.append((g, srv.submit(g.col_ptr, g.row_idx, g.w)))
+            tickets.append((None, srv.submit(bad.col_ptr, r, w)))
+        for wl, t in tickets:
+            res = srv.poll(t)
+            if wl is None:
+                assert res[0] == hwpm.HWPM_EBADCSC and res[1] is None
+            else:
+                _check(wl, res)
+        t = srv.submit(good[0].col_ptr, good[0].row_idx, good[0].w)
         res = None
         deadline = time.time() + 60
         while res is None and time.time() < deadline:
@@ -142,7 +155,7 @@ def test_submit_rejects_bad_matrix_and_poll_semantics():
             if res is None:
                 time.sleep(0.001)
         assert res is not None
-        _check(good, res)
+        _check(good[0], res)
         st, _, _ = hwpm.hwpm_poll(srv.server, t, True, None)  # already delivered
         assert st == hwpm.HWPM_EINVAL
         st, _, _ = hwpm.hwpm_poll(srv.server, 987654321, False, None)

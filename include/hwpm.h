@@ -98,7 +98,11 @@ typedef struct {
      * m_j (the marking trick of Section 4), with per-entry mate columns kept
      * up to date across flips, one entry per lane; 3 = the same with 8
      * entries per lane in 4-lane tiles; 4 = the same with 16-byte vector
-     * loads (used when row_idx is 16-byte aligned, else 3). */
+     * loads (used when row_idx is 16-byte aligned, else 3); 5 = probe 3 over
+     * row lists built without CSC positions (a lighter transpose; a hit or a
+     * mate refresh binary-searches its entry instead: the better choice when
+     * hits are rare).  Probes 2-5 keep 32-bit CSC positions: a matrix with
+     * nnz >= 2^31 uses probe 1. */
     int32_t probe;
     /* Initial matching of hwpm_match (Section 5.2): 0 = heavy-edge tie-break
      * in the greedy and BFS steps (the paper's heuristic, default);
@@ -227,14 +231,15 @@ int hwpm_match(hwpm_handle h, const hwpm_csc* A, int32_t* perm_out, double* tota
 /* ---- tuning ---------------------------------------------------------------
  * Launch-configuration tuner.  Runs hwpm_improve from mate_in once per
  * candidate (probe, tile_width) -- probe 1 with tiles 4, 8, 16, 32, 64,
- * probe 3 with tiles 4, 8, 16, 32, and probe 4 -- twice over, timing each
+ * probe 3 with tiles 4, 8, 16, 32, probe 4, and probe 5 with tiles 4 and
+ * 8 -- twice over, timing each
  * whole call on the host clock, and writes the fastest candidate's probe and
  * tile_width into *opt (its other fields are used as given: max_rounds,
  * full_search, ...).  Outputs never depend on these two fields, so a tuned
  * solve returns exactly what an untuned one does; perm_out holds that result
  * (device int32[n]).  ms_out (host, nullable) receives the best time of each
  * candidate, in the order above.  Errors as hwpm_improve. */
-#define HWPM_TUNE_CANDIDATES 10
+#define HWPM_TUNE_CANDIDATES 12
 int hwpm_autotune(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
                   hwpm_options* opt, float* ms_out, void* workspace, size_t workspace_bytes);
 

@@ -101,11 +101,19 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     // default tile: 4 lanes per root for short columns, 8 from about 20
     // entries per column on (the chunked kernel then holds 32 per tile either way)
     const int tile = opt.tile_width ? opt.tile_width
-                                    : (probe == 3 && A.nnz > 20 * (int64_t)A.n ? 8 : kDefaultTile);
+                                    : ((probe == 3 || probe == 5) && A.nnz > 20 * (int64_t)A.n ? 8 : kDefaultTile);
     // the vector kernel reads row_idx in aligned 16-byte windows
     if (probe == 4 && ((uintptr_t)A.row_idx & 15)) probe = 3;
+    // the row lists keep 32-bit CSC positions
+    if (probe >= 2 && A.nnz >= ((int64_t)1 << 31)) probe = 1;
+    // probe 5: the chunked kernels over row lists built without CSC positions
+    // (a hit or a mate refresh searches its entry's position instead)
+    const bool light = probe == 5 && transpose_without_positions(A.n, A.nnz);
+    if (probe == 5) probe = 3;
     const bool transposed = probe >= 2;
     const bool incremental = probe >= 3 && !opt.full_search;
+    Work Wr = W;  // the round kernels' view of the workspace
+    if (light) Wr.cscpos = nullptr;
     // 2. set-up: mates, matched weights, matching validation, long columns
     if (timing) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(hipMemsetAsync(W.counters, 0, kCounterWords * sizeof(int32_t), s));
@@ -126,7 +134,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     if (transposed) {
         if (timing) HIP_TRY(hipEventRecord(ev[0], s));
         if (incremental) HIP_TRY(hipMemsetAsync(W.dirty, 0, (size_t)n * sizeof(int32_t), s));
-        HIP_TRY(launch_transpose(A, W, kLongThreshold, n_long > 0, s, h->cus));
+        HIP_TRY(launch_transpose(A, W, kLongThreshold, n_long > 0, !light, s, h->cus));
         if (timing) {
             HIP_TRY(hipEventRecord(ev[1], s));
             HIP_TRY(hipEventSynchronize(ev[1]));
@@ -153,14 +161,14 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
             const bool listed = incremental && r > 0;
             hipEvent_t* e = ev + 8 + 4 * b;
             if (timing) HIP_TRY(hipEventRecord(e[0], s));
-            HIP_TRY(launch_search(A, W, tile, kLongThreshold, slot, n_long > 0, probe, listed, incremental, s,
+            HIP_TRY(launch_search(A, Wr, tile, kLongThreshold, slot, n_long > 0, probe, listed, incremental, s,
                                   h->cus));
             if (timing) HIP_TRY(hipEventRecord(e[1], s));
             HIP_TRY(launch_collect(A, W, slot, s, h->cus));
             HIP_TRY(launch_resolve(W, slot, s, h->cus));
             if (timing) HIP_TRY(hipEventRecord(e[2], s));
             HIP_TRY(launch_apply(A, W, slot, transposed, s, h->cus));
-            if (transposed) HIP_TRY(launch_mrk_update(W, slot, incremental, s, h->cus));
+            if (transposed) HIP_TRY(launch_mrk_update(A, Wr, slot, incremental, s, h->cus));
             if (BP) HIP_TRY(launch_item_rounds(*BP, W.counters + kDone, s));
             if (timing) HIP_TRY(hipEventRecord(e[3], s));
             HIP_TRY(launch_round_end(W, slot, r, listed, n, s));
@@ -244,8 +252,8 @@ int check_options(const hwpm_options& opt) {
     const int tile = opt.tile_width ? opt.tile_width : kDefaultTile;
     if (tile != 4 && tile != 8 && tile != 16 && tile != 32 && tile != 64) return HWPM_EINVAL;
     const int probe = opt.probe ? opt.probe : kDefaultProbe;
-    if (probe < 1 || probe > 4) return HWPM_EINVAL;
-    if (probe == 3 && tile == 64) return HWPM_EINVAL;
+    if (probe < 1 || probe > 5) return HWPM_EINVAL;
+    if ((probe == 3 || probe == 5) && tile == 64) return HWPM_EINVAL;
     if (opt.mcm_plain != 0 && opt.mcm_plain != 1) return HWPM_EINVAL;
     if (opt.full_search != 0 && opt.full_search != 1) return HWPM_EINVAL;
     return HWPM_OK;
@@ -784,7 +792,7 @@ static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const i
 int hwpm_autotune(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
                   hwpm_options* opt, float* ms_out, void* workspace, size_t workspace_bytes) {
     static const int32_t kCand[HWPM_TUNE_CANDIDATES][2] = {
-        {1, 4}, {1, 8}, {1, 16}, {1, 32}, {1, 64}, {3, 4}, {3, 8}, {3, 16}, {3, 32}, {4, 4}};
+        {1, 4}, {1, 8}, {1, 16}, {1, 32}, {1, 64}, {3, 4}, {3, 8}, {3, 16}, {3, 32}, {4, 4}, {5, 4}, {5, 8}};
     if (!h || !opt) return HWPM_EINVAL;
     int st = check_options(*opt);
     if (st != HWPM_OK) return st;

@@ -97,7 +97,8 @@ struct Work {
     int64_t* rstart;    // n: start of the row list of the row matched to column j
     int32_t* rlen;      // n: its length
     int32_t* colidx;    // nnz: columns of each row (any order within a row)
-    int64_t* cscpos;    // nnz: CSC position of each row-list entry
+    int32_t* cscpos;    // nnz: CSC position of each row-list entry (transposed probes need nnz < 2^31);
+                        // null when the lists are built without positions (probe 5)
     int32_t* mrk;       // nnz: m_i of the row of CSC entry k
     int32_t* rowcnt;    // n: row counts, then fill cursors
     int64_t* scan_sums; // block sums of the row-count scan
@@ -212,8 +213,9 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
 hipError_t launch_round_end(const Work& W, int slot, int round, bool listed, int32_t n, hipStream_t s);
 hipError_t launch_collect(const Csc& A, const Work& W, int slot, hipStream_t s, int cus);
 hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
-                            hipStream_t s, int cus);
-hipError_t launch_mrk_update(const Work& W, int slot, bool incremental, hipStream_t s, int cus);
+                            bool positions, hipStream_t s, int cus);
+bool transpose_without_positions(int64_t n, int64_t nnz);
+hipError_t launch_mrk_update(const Csc& A, const Work& W, int slot, bool incremental, hipStream_t s, int cus);
 hipError_t launch_resolve(const Work& W, int slot, hipStream_t s, int cus);
 hipError_t launch_apply(const Csc& A, const Work& W, int slot, bool transposed, hipStream_t s,
                         int cus);

@@ -348,7 +348,7 @@ __device__ __forceinline__ void fill_entry(const Csc& A, const Work& W, int32_t 
     const int32_t slot = atomicAdd(&W.rowcnt[r], 1);
     const int64_t e = W.rowptr[r] + slot;
     W.colidx[e] = j;
-    W.cscpos[e] = k;
+    W.cscpos[e] = (int32_t)k;
 }
 
 template <int T>
@@ -492,9 +492,10 @@ __global__ __launch_bounds__(256) void k_tp_hist(Csc A, const int32_t* __restric
 }
 
 // Pass 1b: sort the tile by bucket in LDS, write the triples in runs.
+template <bool POS>
 __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
                                                     const int64_t* __restrict__ off) {
-    __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[kTpTile];
+    __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[kTpMaxBuckets], start[kTpMaxBuckets], base[kTpMaxBuckets];
     __shared__ int32_t wsum[4];
     const int32_t seg = blockIdx.x;
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32
             const int32_t x = start[sl[u] >> rb] + rk[u];
             s_slot[x] = sl[u];
             s_col[x] = co[u];
-            s_pos[x] = (int32_t)(k0 + threadIdx.x + 256 * u);
+            if (POS) s_pos[x] = (int32_t)(k0 + threadIdx.x + 256 * u);
         }
     }
     __syncthreads();
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32
         const int32_t g = base[b] + (e - start[b]);
         W.tp_row[g] = slot;
         W.tp_col[g] = s_col[e];
-        W.tp_pos[g] = s_pos[e];
+        if (POS) W.tp_pos[g] = s_pos[e];
     }
 }
 
@@ -564,9 +565,10 @@ __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32
 // leave in runs, and records where each sub-bucket starts.
 constexpr int kTpSub = 64;
 
+template <bool POS>
 __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
                                                    const int64_t* __restrict__ off) {
-    __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[kTpTile];
+    __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[kTpSub], start[kTpSub], cursor[kTpSub];
     const int32_t b = blockIdx.x;
     const int64_t r0 = (int64_t)b << rb;
@@ -605,7 +607,7 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
             const int32_t x = t + 1024 * u;
             sl[u] = (x < len) ? W.tp_row[t0 + x] : -1;
             co[u] = (x < len) ? W.tp_col[t0 + x] : 0;
-            ps[u] = (x < len) ? W.tp_pos[t0 + x] : 0;
+            ps[u] = (POS && x < len) ? W.tp_pos[t0 + x] : 0;
             if (sl[u] >= 0) rk[u] = atomicAdd(&hist[(sl[u] - r0) >> sb], 1);
         }
         __syncthreads();
@@ -626,7 +628,7 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
                 const int32_t x = start[(sl[u] - r0) >> sb] + rk[u];
                 s_slot[x] = sl[u];
                 s_col[x] = co[u];
-                s_pos[x] = ps[u];
+                if (POS) s_pos[x] = ps[u];
             }
         }
         __syncthreads();
@@ -635,7 +637,7 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
             const int64_t q = e0 + cursor[g] + (x - start[g]);
             W.tp_row2[q] = s_slot[x];
             W.tp_col2[q] = s_col[x];
-            W.tp_pos2[q] = s_pos[x];
+            if (POS) W.tp_pos2[q] = s_pos[x];
         }
         __syncthreads();
         if (t < kTpSub) cursor[t] += hist[t];
@@ -650,11 +652,12 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
 // and written as one run per slot.
 constexpr int kPlaceTile = 2048;  // entries per LDS tile (256 threads x 8)
 
+template <bool POS>
 __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t nb) {
     constexpr int NS = kTpMaxRows / kTpSub;  // slots per sub-bucket, at most 128
     constexpr int U = kPlaceTile / 256;
     __shared__ int32_t rc[NS], tc[NS], ts[NS];
-    __shared__ int32_t s_key[kPlaceTile], s_col[kPlaceTile], s_pos[kPlaceTile];
+    __shared__ int32_t s_key[kPlaceTile], s_col[kPlaceTile], s_pos[POS ? kPlaceTile : 1];
     const int32_t g = blockIdx.x;
     const int32_t b = g / kTpSub, sub = g % kTpSub;
     const int sb = rb - 6;
@@ -678,7 +681,7 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
             key[u] = ok ? (int32_t)(W.tp_row2[e0 + x] - s0) : 0;
             if (one_tile) {
                 col[u] = ok ? W.tp_col2[e0 + x] : 0;
-                pos[u] = ok ? W.tp_pos2[e0 + x] : 0;
+                pos[u] = (POS && ok) ? W.tp_pos2[e0 + x] : 0;
             }
             if (ok) rk[u] = atomicAdd(&rc[key[u]], 1);
         }
@@ -715,13 +718,13 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
             if (rk[u] >= 0) {
                 const int32_t d = rc[key[u]] + rk[u];
                 s_col[d] = col[u];
-                s_pos[d] = pos[u];
+                if (POS) s_pos[d] = pos[u];
             }
         }
         __syncthreads();
         for (int32_t x = t; x < (int32_t)len; x += 256) {
             W.colidx[e0 + x] = s_col[x];
-            W.cscpos[e0 + x] = s_pos[x];
+            if (POS) W.cscpos[e0 + x] = s_pos[x];
         }
         return;
     }
@@ -735,7 +738,7 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
             const bool ok = x < tl;
             key[u] = ok ? (int32_t)(W.tp_row2[e0 + c0 + x] - s0) : 0;
             col[u] = ok ? W.tp_col2[e0 + c0 + x] : 0;
-            pos[u] = ok ? W.tp_pos2[e0 + c0 + x] : 0;
+            pos[u] = (POS && ok) ? W.tp_pos2[e0 + c0 + x] : 0;
             rk[u] = ok ? atomicAdd(&tc[key[u]], 1) : -1;
         }
         __syncthreads();
@@ -749,7 +752,7 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
                 const int32_t d = ts[key[u]] + rk[u];
                 s_key[d] = key[u];
                 s_col[d] = col[u];
-                s_pos[d] = pos[u];
+                if (POS) s_pos[d] = pos[u];
             }
         }
         __syncthreads();
@@ -757,7 +760,7 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
             const int32_t k = s_key[x];
             const int64_t dst = e0 + rc[k] + (x - ts[k]);
             W.colidx[dst] = s_col[x];
-            W.cscpos[dst] = s_pos[x];
+            if (POS) W.cscpos[dst] = s_pos[x];
         }
         __syncthreads();
         if (t < NS) rc[t] += tc[t];
@@ -766,7 +769,7 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
 }
 
 hipError_t launch_transpose_buckets(const Csc& A, const Work& W, int32_t long_threshold,
-                                    bool has_long, hipStream_t s, int cus) {
+                                    bool has_long, bool positions, hipStream_t s, int cus) {
     const TpPlan P = tp_plan(A.n, A.nnz);
     const int32_t nb = (int32_t)P.nb, nseg = (int32_t)P.nseg;
     const int64_t m = P.nb * P.nseg;
@@ -779,19 +782,27 @@ hipError_t launch_transpose_buckets(const Csc& A, const Work& W, int32_t long_th
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)sb), dim3(256), 0, s, W.tp_cnt, m, W.tp_off, W.tp_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, W.tp_sums, sb, W.tp_off + m);
     hipLaunchKernelGGL(k_scan_add, dim3(cus * 8), dim3(256), 0, s, W.tp_off, m, W.tp_sums);
-    hipLaunchKernelGGL(k_tp_scatter, dim3(nseg), dim3(256), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-    hipLaunchKernelGGL(k_tp_split, dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-    hipLaunchKernelGGL(k_tp_place, dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
+    if (positions) {
+        hipLaunchKernelGGL(k_tp_scatter<true>, dim3(nseg), dim3(256), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+        hipLaunchKernelGGL(k_tp_split<true>, dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+        hipLaunchKernelGGL(k_tp_place<true>, dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
+    } else {
+        hipLaunchKernelGGL(k_tp_scatter<false>, dim3(nseg), dim3(256), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+        hipLaunchKernelGGL(k_tp_split<false>, dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+        hipLaunchKernelGGL(k_tp_place<false>, dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
+    }
     return hipGetLastError();
 }
 
+bool transpose_without_positions(int64_t n, int64_t nnz) { return tp_plan(n, nnz).ok; }
+
 hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
-                            hipStream_t s, int cus) {
+                            bool positions, hipStream_t s, int cus) {
     const int64_t n = A.n;
     hipError_t e;
     if (tp_plan(A.n, A.nnz).ok) {
         // also fills mrk
-        return launch_transpose_buckets(A, W, long_threshold, has_long, s, cus);
+        return launch_transpose_buckets(A, W, long_threshold, has_long, positions, s, cus);
     } else {
         // very large matrices: counting sort with global atomics
         if ((e = hipMemsetAsync(W.rowcnt, 0, (size_t)n * sizeof(int32_t), s)) != hipSuccess) return e;
@@ -822,9 +833,11 @@ hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold,
 // appear in the lists of their new rows.
 constexpr int32_t kHeavyRow = 4096;
 
-__device__ __forceinline__ void refresh_entry(const Work& W, int64_t x, int32_t m, int incremental,
-                                              int next) {
-    W.mrk[W.cscpos[x]] = m;
+__device__ __forceinline__ void refresh_entry(const Csc& A, const Work& W, int64_t x, int32_t m, int32_t row,
+                                              int incremental, int next) {
+    // entry {row, colidx[x]}: its CSC position is stored, or searched for
+    const int64_t pos = W.cscpos ? (int64_t)W.cscpos[x] : find_row(A.col_ptr, A.row_idx, W.colidx[x], row);
+    W.mrk[pos] = m;
     if (incremental) {
         const int32_t c = W.colidx[x];
         const bool first = __hip_atomic_load(&W.dirty[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0 &&
@@ -834,7 +847,7 @@ __device__ __forceinline__ void refresh_entry(const Work& W, int64_t x, int32_t 
     }
 }
 
-__global__ __launch_bounds__(256) void k_mrk_update(Work W, int slot, int incremental) {
+__global__ __launch_bounds__(256) void k_mrk_update(Csc A, Work W, int slot, int incremental) {
     if (round_over(W)) return;
     const int64_t nf = 2 * (int64_t)W.counters[slot_word(slot, kApplied)];
     const int next = (slot + 1) % kSlots;
@@ -846,11 +859,13 @@ __global__ __launch_bounds__(256) void k_mrk_update(Work W, int slot, int increm
             if (threadIdx.x == 0) W.heavy[atomicAdd(&W.counters[slot_word(slot, kHeavy)], 1)] = m;
             continue;
         }
-        for (int64_t x = b + threadIdx.x; x < b + len; x += blockDim.x) refresh_entry(W, x, m, incremental, next);
+        const int32_t row = W.mc[m];  // the row now matched to m owns the list
+        for (int64_t x = b + threadIdx.x; x < b + len; x += blockDim.x)
+            refresh_entry(A, W, x, m, row, incremental, next);
     }
 }
 
-__global__ __launch_bounds__(256) void k_mrk_update_heavy(Work W, int slot, int incremental) {
+__global__ __launch_bounds__(256) void k_mrk_update_heavy(Csc A, Work W, int slot, int incremental) {
     if (round_over(W)) return;
     const int32_t nh = W.counters[slot_word(slot, kHeavy)];
     const int next = (slot + 1) % kSlots;
@@ -858,8 +873,9 @@ __global__ __launch_bounds__(256) void k_mrk_update_heavy(Work W, int slot, int 
     for (int32_t h = 0; h < nh; ++h) {
         const int32_t m = W.heavy[h];
         const int64_t b = W.rstart[m], e = b + W.rlen[m];
+        const int32_t row = W.mc[m];
         for (int64_t x = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < e; x += stride)
-            refresh_entry(W, x, m, incremental, next);
+            refresh_entry(A, W, x, m, row, incremental, next);
     }
 }
 
@@ -886,9 +902,9 @@ hipError_t launch_round_end(const Work& W, int slot, int round, bool listed, int
     return hipGetLastError();
 }
 
-hipError_t launch_mrk_update(const Work& W, int slot, bool incremental, hipStream_t s, int cus) {
-    hipLaunchKernelGGL(k_mrk_update, dim3(cus * 4), dim3(256), 0, s, W, slot, incremental ? 1 : 0);
-    hipLaunchKernelGGL(k_mrk_update_heavy, dim3(cus * 4), dim3(256), 0, s, W, slot, incremental ? 1 : 0);
+hipError_t launch_mrk_update(const Csc& A, const Work& W, int slot, bool incremental, hipStream_t s, int cus) {
+    hipLaunchKernelGGL(k_mrk_update, dim3(cus * 4), dim3(256), 0, s, A, W, slot, incremental ? 1 : 0);
+    hipLaunchKernelGGL(k_mrk_update_heavy, dim3(cus * 4), dim3(256), 0, s, A, W, slot, incremental ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -998,7 +1014,7 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.rstart = (int64_t*)take(N * 8);
     W.rlen = (int32_t*)take(N * 4);
     W.colidx = (int32_t*)take(Z * 4 + 128);
-    W.cscpos = (int64_t*)take(Z * 8);
+    W.cscpos = (int32_t*)take(Z * 4);
     W.mrk = (int32_t*)take(Z * 4 + 128);
     W.rowcnt = (int32_t*)take(N * 4);
     W.scan_sums = (int64_t*)take((N / 2048 + 2) * 8);

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
                     h = (h + 1) & mask;
                 }
                 if (qx < 0) continue;
-                const int64_t p = W.cscpos[rs + qx];
+                const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + qx] : find_row(A.col_ptr, A.row_idx, mi, mj);
                 const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
                 if (g > 0.0 && better(g, i, b.g, b.i)) {
                     b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
@@ -204,7 +204,7 @@ __global__ __launch_bounds__(256) void k_search_rows(Csc A, Work W, int32_t long
                 }
             }
             if (q >= 0) {
-                const int64_t p = W.cscpos[rs + q];
+                const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + q] : find_row(A.col_ptr, A.row_idx, mi, mj);
                 const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
                 if (g > 0.0 && better(g, i, b.g, b.i)) {
                     b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
             for (int e = 0; e < E; ++e) {
                 if (qv[e] >= 0) {
                     const int64_t k = lo + lane + T * e;
-                    const int64_t p = W.cscpos[rs + qv[e]];
+                    const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + qv[e]] : find_row(A.col_ptr, A.row_idx, mv[e], mj);
                     const double g = (A.w[k] + A.w[p]) - (W.wm[mv[e]] + wmj);
                     if (g > 0.0 && better(g, iv[e], b.g, b.i)) {
                         b.g = g; b.i = iv[e]; b.c = mv[e]; b.k = k; b.p = p;
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot) 
                     h = (h + 1) & mask;
                 }
                 if (qx < 0) continue;
-                const int64_t p = W.cscpos[rs + qx];
+                const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + qx] : find_row(A.col_ptr, A.row_idx, mi, mj);
                 const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
                 if (g > 0.0 && better(g, i, b.g, b.i)) {
                     b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_
             for (int e = 0; e < E; ++e) {
                 if (qv[e] >= 0) {
                     const int64_t k = cb + 16 * (e >> 2) + 4 * lane + (e & 3);
-                    const int64_t p = W.cscpos[rb + qv[e]];
+                    const int64_t p = W.cscpos ? (int64_t)W.cscpos[rb + qv[e]] : find_row(A.col_ptr, A.row_idx, mv[e], mj);
                     const double g = (A.w[k] + A.w[p]) - (W.wm[mv[e]] + wmj);
                     if (g > 0.0 && better(g, iv[e], b.g, b.i)) {
                         b.g = g; b.i = iv[e]; b.c = mv[e]; b.k = k; b.p = p;

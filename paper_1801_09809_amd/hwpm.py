@@ -28,8 +28,9 @@ HWPM_EDEVICE = -7
 HWPM_EINTERNAL = -8
 HWPM_PENDING = 1
 MAX_ROUND_STATS = 512
-TUNE_CANDIDATES = 10
-TUNE_CONFIGS = ((1, 4), (1, 8), (1, 16), (1, 32), (1, 64), (3, 4), (3, 8), (3, 16), (3, 32), (4, 4))
+TUNE_CANDIDATES = 12
+TUNE_CONFIGS = ((1, 4), (1, 8), (1, 16), (1, 32), (1, 64), (3, 4), (3, 8), (3, 16), (3, 32), (4, 4),
+                (5, 4), (5, 8))
 
 EXPORTED = (
     "hwpm_default_options", "hwpm_strerror", "hwpm_create", "hwpm_destroy",

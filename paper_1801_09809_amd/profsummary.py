@@ -3,7 +3,9 @@ folder, and derive the HBM traffic of a kernel from two counter passes.
 
     python -m paper_1801_09809_amd.profsummary trace RESULTS.db --command "..."
     python -m paper_1801_09809_amd.profsummary traffic --fetch FETCH.db --write WRITE.db \
-        --kernel k_search_chunk,k_search_medium --name search_stage --copy-bytes N --source csrc/hwpm_kernels.hip --out profiles/traffic.json
+        --kernel k_search_chunk,k_search_medium --name search_stage --copy-bytes N \
+        --source csrc/hwpm_search.hip,csrc/hwpm_device.h,csrc/hwpm_internal.h \
+        --workload random_n1048576_d16 --probe 3 --out profiles/traffic.json
 
 Reads only the SQLite files rocprofv3 writes (views `kernels` and
 `counters_collection`).  Counter values are summed over the rows of one
@@ -103,7 +105,10 @@ def cmd_traffic(args) -> int:
     """Traffic of one stage: the kernels named by --kernel (comma-separated
     substrings), each launched once per stage; their per-dispatch averages add."""
     keys = [k for k in args.kernel.split(",") if k]
-    sha = hashlib.sha256(open(args.source, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in args.source.split(","):
+        h.update(open(f, "rb").read())
+    sha = h.hexdigest()[:16]
     kernels = {}
     read_b = write_b = 0.0
     f_copy = w_copy = f_fac = w_fac = None
@@ -117,7 +122,7 @@ def cmd_traffic(args) -> int:
     rec = {"kernels": kernels, "kernel_src_sha": sha, "bytes_per_launch": read_b + write_b,
            "read_bytes_per_launch": read_b, "write_bytes_per_launch": write_b,
            "copy_bytes": args.copy_bytes, "copy_fetch_kib": f_copy, "copy_write_kib": w_copy,
-           "fetch_factor": f_fac, "write_factor": w_fac, "workload": args.workload, "command": args.command}
+           "fetch_factor": f_fac, "write_factor": w_fac, "workload": args.workload, "probe": args.probe, "command": args.command}
     data = {}
     try:
         with open(args.out) as f:
@@ -145,9 +150,11 @@ def main(argv=None) -> int:
     r.add_argument("--kernel", required=True, help="comma-separated substrings, one per kernel of the stage")
     r.add_argument("--name", required=True, help="key of the record in the output file")
     r.add_argument("--copy-bytes", type=int, required=True, help="bytes of each calibration copy")
-    r.add_argument("--source", required=True, help="source file of the kernel (its hash is recorded)")
+    r.add_argument("--source", required=True,
+                   help="comma-separated source files of the kernels (their joint hash is recorded)")
     r.add_argument("--out", required=True)
     r.add_argument("--workload", required=True, help="name of the workload the passes ran on")
+    r.add_argument("--probe", type=int, required=True, help="the probe the passes ran with")
     r.add_argument("--command", default="")
     args = ap.parse_args(argv)
     return cmd_trace(args) if args.cmd == "trace" else cmd_traffic(args)

@@ -95,10 +95,11 @@ def test_golden_on_gpu(solver, case):
 
 # search configurations: column binary search; transposed row lists; chunked
 # transposed (incremental rounds, the default); chunked with full rounds
-PROBES = ["p1", "p2", "p3", "p3full", "p4", "p4full"]
+PROBES = ["p1", "p2", "p3", "p3full", "p4", "p4full", "p5", "p5full"]
 _PROBE_KW = {"p1": dict(probe=1), "p2": dict(probe=2), "p3": dict(probe=3),
              "p3full": dict(probe=3, full_search=True), "p4": dict(probe=4),
-             "p4full": dict(probe=4, full_search=True)}
+             "p4full": dict(probe=4, full_search=True), "p5": dict(probe=5),
+             "p5full": dict(probe=5, full_search=True)}
 
 
 @pytest.mark.parametrize("probe", PROBES)
@@ -116,7 +117,7 @@ def test_random_vs_oracle(solver, n, d, seed, intw, probe):
 @pytest.mark.parametrize("probe", PROBES)
 @pytest.mark.parametrize("tile", [4, 8, 16, 32, 64])
 def test_tile_widths_identical(solver, tile, probe):
-    if probe[:2] in ("p3", "p4") and tile == 64:
+    if probe[:2] in ("p3", "p4", "p5") and tile == 64:
         pytest.skip("the chunked kernel takes tiles of 4 to 32 lanes")
     if probe[:2] == "p4" and tile != 4:
         pytest.skip("the vector kernel always uses 4-lane tiles")
@@ -317,6 +318,9 @@ def test_full_rmat_converged_properties(solver):
     assert np.array_equal(other[0], perm) and other[1] == total
     assert other[2]["round_applied"] == st["round_applied"]
     assert st["hit_round_cap"] == 0 and st["rounds"] > 3
+    _, light = _full(solver, 3, probe="p5")  # lists without positions: searched mate refreshes
+    assert np.array_equal(light[0], perm) and light[1] == total
+    assert light[2]["round_applied"] == st["round_applied"]
     assert np.array_equal(np.sort(perm), np.arange(wl.n))
     bad, wm = _no_positive_4cycle(wl, perm)
     assert bad == 0
@@ -452,7 +456,7 @@ def _mixed_batch(seed, count=9):
     return out
 
 
-@pytest.mark.parametrize("probe", ["p1", "p3", "p4"])
+@pytest.mark.parametrize("probe", ["p1", "p3", "p4", "p5"])
 def test_improve_batch_equals_alone(solver, probe):
     from oracle import oracle_improve
     dev = solver.device

@@ -469,10 +469,11 @@ __device__ __forceinline__ void wave_scan128(int32_t* cnt) {
     }
 }
 
-// Pass 1a: per-(bucket, tile) counts, written bucket-major.  The slot of
-// every entry (mrk) is filled beforehand by k_mrk_fill.
-__global__ __launch_bounds__(256) void k_tp_hist(Csc A, const int32_t* __restrict__ mrk, int rb,
-                                                 int32_t nb, int32_t nseg, int32_t* __restrict__ cnt) {
+// Pass 1a: the slot of every entry (mrk[k] = m_i of its row, the mate
+// column the search streams) and the per-(bucket, tile) counts, written
+// bucket-major.
+__global__ __launch_bounds__(256) void k_tp_hist(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
+                                                 int32_t* __restrict__ cnt) {
     __shared__ int32_t hist[kTpMaxBuckets];
     for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
@@ -482,7 +483,15 @@ __global__ __launch_bounds__(256) void k_tp_hist(Csc A, const int32_t* __restric
 #pragma unroll
     for (int u = 0; u < kTpTile / 256; ++u) {
         const int64_t k = k0 + threadIdx.x + 256 * u;
-        sl[u] = (k < A.nnz) ? mrk[k] : -1;
+        sl[u] = (k < A.nnz) ? A.row_idx[k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kTpTile / 256; ++u) {
+        const int64_t k = k0 + threadIdx.x + 256 * u;
+        if (sl[u] >= 0) {
+            sl[u] = W.mr[sl[u]];
+            W.mrk[k] = sl[u];
+        }
     }
 #pragma unroll
     for (int u = 0; u < kTpTile / 256; ++u)
@@ -776,8 +785,7 @@ hipError_t launch_transpose_buckets(const Csc& A, const Work& W, int32_t long_th
     const unsigned tiles = (unsigned)(((int64_t)A.n * 16 + 255) / 256);
     hipLaunchKernelGGL(k_colof_short<16>, dim3(tiles), dim3(256), 0, s, A, W, long_threshold);
     if (has_long) hipLaunchKernelGGL(k_colof_long, dim3(cus * 8), dim3(256), 0, s, A, W);
-    hipLaunchKernelGGL(k_mrk_fill, dim3(cus * 8), dim3(256), 0, s, A, W);
-    hipLaunchKernelGGL(k_tp_hist, dim3(nseg), dim3(256), 0, s, A, W.mrk, P.rb, nb, nseg, W.tp_cnt);
+    hipLaunchKernelGGL(k_tp_hist, dim3(nseg), dim3(256), 0, s, A, W, P.rb, nb, nseg, W.tp_cnt);
     const int64_t sb = (m + 2047) / 2048;
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)sb), dim3(256), 0, s, W.tp_cnt, m, W.tp_off, W.tp_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, W.tp_sums, sb, W.tp_off + m);

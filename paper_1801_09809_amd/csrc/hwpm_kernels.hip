@@ -74,10 +74,9 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
         W.dgain[j] = 0ull;
         W.droot[j] = kNoRoot;
         const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
-        if (hi - lo > long_threshold) {
-            const int32_t q = atomicAdd(&W.counters[kNumLong], 1);
-            W.long_list[q] = j;
-        }
+        const bool is_long = hi - lo > long_threshold;
+        const int32_t q = wave_append(&W.counters[kNumLong], is_long);
+        if (is_long) W.long_list[q] = j;
         const int32_t r = mate_in[j];
         if (r < 0 || r >= A.n) {
             atomicOr(&W.counters[kErrMatch], 1);

@@ -45,10 +45,9 @@ __global__ void k_mcm_init(Csc A, Mcm M) {
 __global__ void k_classify_long(Csc A, Work W, int32_t long_threshold) {
     for (int64_t jj = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; jj < A.n;
          jj += (int64_t)gridDim.x * blockDim.x) {
-        if (A.col_ptr[jj + 1] - A.col_ptr[jj] > long_threshold) {
-            const int32_t q = atomicAdd(&W.counters[kNumLong], 1);
-            W.long_list[q] = (int32_t)jj;
-        }
+        const bool is_long = A.col_ptr[jj + 1] - A.col_ptr[jj] > long_threshold;
+        const int32_t q = wave_append(&W.counters[kNumLong], is_long);
+        if (is_long) W.long_list[q] = (int32_t)jj;
     }
 }
 
@@ -308,8 +307,8 @@ __global__ void k_bfs_augment(Csc A, Mcm M) {
     for (int64_t tt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; tt < A.n;
          tt += (int64_t)gridDim.x * blockDim.x) {
         int32_t r = M.end_row[tt];
+        wave_append(&M.counters[kMcmAugmented], r != kNoRoot);  // counts the paths
         if (r == kNoRoot) continue;
-        atomicAdd(&M.counters[kMcmAugmented], 1);
         while (r >= 0) {
             const int32_t c = M.parent[r];
             const int32_t r_next = M.mc[c];

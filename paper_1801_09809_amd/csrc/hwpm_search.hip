@@ -255,7 +255,14 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
         const double wmj = W.wm[j];
         const int64_t rs = W.rstart[j];
         const int32_t rlen = W.rlen[j];
-        if (len <= T * E && rlen <= T * E) {
+        // a root too long for the tile goes to the wave-per-root kernel
+        const bool handoff = len > T * E || rlen > T * E;
+        const int32_t q = wave_append(&W.counters[slot_word(slot, kMedium)], handoff && lane == 0);
+        if (handoff) {
+            if (lane == 0) W.medium[q] = j;
+            return;  // tile-uniform
+        }
+        {
             int32_t iv[E], mv[E], rv[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -294,10 +301,6 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
                     }
                 }
             }
-        } else {
-            // too long for the tile: one wave per root searches it
-            if (lane == 0) W.medium[atomicAdd(&W.counters[slot_word(slot, kMedium)], 1)] = j;
-            return;  // tile-uniform
         }
     }
     reduce_best<T>(b);
@@ -428,7 +431,14 @@ __global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_
         const int64_t rs = W.rstart[j];
         const int32_t rlen = W.rlen[j];
         const int64_t cb = lo & ~(int64_t)3, rb = rs & ~(int64_t)3;
-        if (hi <= cb + 32 && rs + rlen <= rb + 32 && cb + 32 <= A.nnz) {
+        // a segment that does not fit its window goes to the wave-per-root kernel
+        const bool handoff = !(hi <= cb + 32 && rs + rlen <= rb + 32 && cb + 32 <= A.nnz);
+        const int32_t q = wave_append(&W.counters[slot_word(slot, kMedium)], handoff && lane == 0);
+        if (handoff) {
+            if (lane == 0) W.medium[q] = j;
+            return;  // tile-uniform
+        }
+        {
             const int4 i0 = ld4(A.row_idx + cb + 4 * lane), i1 = ld4(A.row_idx + cb + 16 + 4 * lane);
             const int4 m0 = ld4(W.mrk + cb + 4 * lane), m1 = ld4(W.mrk + cb + 16 + 4 * lane);
             const int4 r0 = ld4(W.colidx + rb + 4 * lane), r1 = ld4(W.colidx + rb + 16 + 4 * lane);
@@ -468,9 +478,6 @@ __global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_
                     }
                 }
             }
-        } else {
-            if (lane == 0) W.medium[atomicAdd(&W.counters[slot_word(slot, kMedium)], 1)] = j;
-            return;  // tile-uniform
         }
     }
     reduce_best<T>(b);

@@ -86,7 +86,11 @@ typedef struct {
      * passed hwpm_check_csc).  Kernels index with the given arrays, so a
      * malformed CSC with check_csc = 0 is undefined behaviour. */
     int32_t check_csc;
-    /* 1 = time every stage with HIP events into hwpm_stats (ms_*). */
+    /* 0 = no timing; 1 = time every stage with HIP events into hwpm_stats
+     * (ms_*); 2 = time the search stage (Steps A-C) only: ms_search,
+     * ms_search_first and round_ms_search, two events per round (an event
+     * between two kernels also holds the second one back, so fewer events
+     * perturb the solve less).  Other values: HWPM_EINVAL. */
     int32_t timing;
     /* Lanes per column in the cycle-search kernel: 0 = default (4; 8 with
      * probe 3 when the matrix has more than 20 entries per column on
@@ -129,7 +133,8 @@ typedef struct {
     int32_t mcm_levels;      /* hwpm_match: BFS levels over all phases */
     double init_weight;      /* total weight of the starting perfect matching */
     double final_weight;     /* = *total_out */
-    /* milliseconds, filled when options.timing = 1 (else 0; ms_total always) */
+    /* milliseconds, filled when options.timing = 1 (else 0; ms_total always;
+     * the three search-stage fields also when options.timing = 2) */
     float ms_check;          /* CSC validation */
     float ms_greedy;         /* hwpm_match: greedy maximal matching */
     float ms_mcm;            /* hwpm_match: BFS phases */
@@ -145,7 +150,7 @@ typedef struct {
     /* per round (first HWPM_MAX_ROUND_STATS rounds) */
     int32_t round_candidates[HWPM_MAX_ROUND_STATS]; /* roots that kept a cycle (Step C) */
     int32_t round_applied[HWPM_MAX_ROUND_STATS];    /* cycles flipped (Step D) */
-    float round_ms_search[HWPM_MAX_ROUND_STATS];    /* Steps A-C time, when timing = 1 */
+    float round_ms_search[HWPM_MAX_ROUND_STATS];    /* Steps A-C time, when timing = 1 or 2 */
     int32_t round_roots[HWPM_MAX_ROUND_STATS];      /* columns searched */
 } hwpm_stats;
 

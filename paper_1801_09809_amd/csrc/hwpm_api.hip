@@ -18,7 +18,7 @@ struct hwpm_handle_s {
     int32_t* host;        // pinned host buffer for counter / result readback
     // 0-7: stage events; 8 + 4*b .. 8 + 4*b + 3: the stages of the b-th
     // round of a batch of queued rounds
-    hipEvent_t ev[8 + 4 * kSlots];
+    hipEvent_t ev[8 + 8 * kSlots];  // 8 stage events, two sets of 4 per round of a batch
 };
 
 namespace {
@@ -95,7 +95,8 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     hwpm_stats& S = *Sp;
     const int32_t n = A.n;
     hipStream_t s = h->stream;
-    const bool timing = opt.timing != 0;
+    const bool timing = opt.timing == 1;   // every stage
+    const bool tsearch = opt.timing != 0;  // the search stage (both levels)
     hipEvent_t* ev = h->ev;
     int probe = opt.probe ? opt.probe : kDefaultProbe;
     // default tile: 4 lanes per root for short columns, 8 from about 20
@@ -124,7 +125,6 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[1], sizeof(double), hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[1], s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (timing) S.ms_setup = elapsed(ev[0], ev[1]);
     if (h->host[kErrMatch]) return HWPM_EBADMATCH;
     if (BP) HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_init, s, h->cus));
     const int32_t n_long = h->host[kNumLong];
@@ -132,38 +132,54 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     S.long_columns = n_long;
     memcpy(&S.init_weight, h->host + kHostScalar, sizeof(double));
     if (transposed) {
-        if (timing) HIP_TRY(hipEventRecord(ev[0], s));
+        if (timing) HIP_TRY(hipEventRecord(ev[2], s));
         if (incremental) HIP_TRY(hipMemsetAsync(W.dirty, 0, (size_t)n * sizeof(int32_t), s));
         HIP_TRY(launch_transpose(A, W, kLongThreshold, n_long > 0, !light, s, h->cus));
-        if (timing) {
-            HIP_TRY(hipEventRecord(ev[1], s));
-            HIP_TRY(hipEventSynchronize(ev[1]));
-            S.ms_transpose = elapsed(ev[0], ev[1]);
-        }
+        if (timing) HIP_TRY(hipEventRecord(ev[3], s));  // read at the end
     }
 
     // 3. rounds.  In incremental mode the first round searches every root and
     // later rounds only the roots the previous flips touched (the others keep
     // their Step-C records, which cannot have changed).  Rounds are queued in
-    // batches of 1, 1, 2, 4, 8, 8, ... with no host round trip inside a
+    // batches of 2, 4, 8, 8, ... with no host round trip inside a
     // batch: the round that flips nothing raises a device flag and every
     // round kernel queued after it returns at once.
+    // With timing, a batch's events are read while the next batch (or the
+    // output stage) runs: the batches alternate between two event sets.
     int32_t round = 0;  // rounds queued
-    int32_t batch = 1;
+    int32_t batch = 2;
     int32_t done = 0, rounds_run = 0;
+    int32_t batches = 0;
+    int32_t pend_first = 0, pend_nb = 0, pend_ran = 0, pend_set = 0;  // a batch whose events are unread
+    auto read_round_events = [&]() {
+        for (int32_t b = 0; b < pend_nb; ++b) {
+            const int32_t r = pend_first + b;
+            if (r >= pend_ran) break;  // queued after the loop ended: did nothing
+            hipEvent_t* e = ev + 8 + 4 * (kSlots * pend_set + b);
+            const float ms = elapsed(e[0], e[1]);
+            S.ms_search += ms;
+            if (r == 0) S.ms_search_first = ms;
+            if (r < HWPM_MAX_ROUND_STATS) S.round_ms_search[r] = ms;
+            if (!timing) continue;
+            S.ms_resolve += elapsed(e[1], e[2]);
+            S.ms_apply += elapsed(e[2], e[3]);
+        }
+        pend_nb = 0;
+    };
     for (;;) {
         int32_t nb = batch;
         if (opt.max_rounds > 0 && opt.max_rounds - round < nb) nb = opt.max_rounds - round;
         if (nb <= 0) break;  // the round cap
+        const int32_t set = batches & 1;
         for (int32_t b = 0; b < nb; ++b) {
             const int32_t r = round + b;
             const int slot = r % kSlots;
             const bool listed = incremental && r > 0;
-            hipEvent_t* e = ev + 8 + 4 * b;
-            if (timing) HIP_TRY(hipEventRecord(e[0], s));
+            hipEvent_t* e = ev + 8 + 4 * (kSlots * set + b);
+            if (tsearch) HIP_TRY(hipEventRecord(e[0], s));
             HIP_TRY(launch_search(A, Wr, tile, kLongThreshold, slot, n_long > 0, probe, listed, incremental, s,
                                   h->cus));
-            if (timing) HIP_TRY(hipEventRecord(e[1], s));
+            if (tsearch) HIP_TRY(hipEventRecord(e[1], s));
             HIP_TRY(launch_collect(A, W, slot, s, h->cus));
             HIP_TRY(launch_resolve(W, slot, s, h->cus));
             if (timing) HIP_TRY(hipEventRecord(e[2], s));
@@ -174,28 +190,21 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
             HIP_TRY(launch_round_end(W, slot, r, listed, n, s));
         }
         round += nb;
+        ++batches;
         HIP_TRY(hipMemcpyAsync(h->host, W.counters + kDone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        if (tsearch) read_round_events();  // the previous batch's, while this one runs
         HIP_TRY(hipStreamSynchronize(s));
         done = h->host[0];
         rounds_run = h->host[1];
-        if (timing) {
-            for (int32_t b = 0; b < nb; ++b) {
-                const int32_t r = round - nb + b;
-                if (r >= rounds_run) break;
-                hipEvent_t* e = ev + 8 + 4 * b;
-                const float ms = elapsed(e[0], e[1]);
-                S.ms_search += ms;
-                if (r == 0) S.ms_search_first = ms;
-                if (r < HWPM_MAX_ROUND_STATS) S.round_ms_search[r] = ms;
-                S.ms_resolve += elapsed(e[1], e[2]);
-                S.ms_apply += elapsed(e[2], e[3]);
-            }
-        }
+        pend_first = round - nb;
+        pend_nb = nb;
+        pend_ran = rounds_run;
+        pend_set = set;
         // A round with candidates always flips at least one cycle (the
         // candidate whose other column has the largest matched row).
         if (done == 2) return HWPM_EINTERNAL;
         if (done) break;
-        batch = round < 2 ? 1 : (2 * batch < kSlots ? 2 * batch : kSlots);
+        batch = 2 * batch < kSlots ? 2 * batch : kSlots;
     }
     if (!done) S.hit_round_cap = 1;
     S.rounds = done ? rounds_run : round;
@@ -217,6 +226,11 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     }
     HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[7], s));
+    if (tsearch) read_round_events();  // while the output stage runs
+    if (timing) {
+        S.ms_setup = elapsed(ev[0], ev[1]);
+        if (transposed) S.ms_transpose = elapsed(ev[2], ev[3]);
+    }
     HIP_TRY(hipStreamSynchronize(s));
     if (timing) S.ms_final = elapsed(ev[6], ev[7]);
     unsigned long long cycles = 0;
@@ -256,6 +270,7 @@ int check_options(const hwpm_options& opt) {
     if ((probe == 3 || probe == 5) && tile == 64) return HWPM_EINVAL;
     if (opt.mcm_plain != 0 && opt.mcm_plain != 1) return HWPM_EINVAL;
     if (opt.full_search != 0 && opt.full_search != 1) return HWPM_EINVAL;
+    if (opt.timing < 0 || opt.timing > 2) return HWPM_EINVAL;
     return HWPM_OK;
 }
 
@@ -539,7 +554,9 @@ int hwpm_create(hwpm_handle* out, int device, void* stream) {
     int ne = 0;
     bool ok = hipHostMalloc((void**)&h->host, kHostBytes, hipHostMallocDefault) == hipSuccess;
     while (ok && ne < kEvents) {
-        ok = hipEventCreate(&h->ev[ne]) == hipSuccess;
+        // timing only (host data is always read after a stream synchronize):
+        // no system-scope cache flush at each record
+        ok = hipEventCreateWithFlags(&h->ev[ne], hipEventDisableSystemFence) == hipSuccess;
         if (ok) ++ne;
     }
     if (!ok) {
@@ -614,7 +631,7 @@ int hwpm_improve(hwpm_handle h, const hwpm_csc* Ain, const int32_t* mate_in, int
     Work W;
     workspace_layout(n, A.nnz, (char*)workspace, &W);
     if (opt.check_csc) {
-        st = timed_check(h, A, W, opt.timing != 0, &S);
+        st = timed_check(h, A, W, opt.timing == 1, &S);
         if (st != HWPM_OK) return st;
     }
     double total = 0.0;
@@ -656,7 +673,7 @@ int hwpm_match(hwpm_handle h, const hwpm_csc* Ain, int32_t* perm_out, double* to
     Work W;
     Mcm M;
     workspace_layout(n, A.nnz, (char*)workspace, &W, &M);
-    const bool timing = opt.timing != 0;
+    const bool timing = opt.timing == 1;
     if (opt.check_csc) {
         st = timed_check(h, A, W, timing, &S);
         if (st != HWPM_OK) return st;
@@ -732,13 +749,13 @@ static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const i
     A.w = P.w;
     if (h->host[0] & 3) return HWPM_EBADCSC;
     if (opt.check_csc) {
-        st = timed_check(h, A, W, opt.timing != 0, &S);
+        st = timed_check(h, A, W, opt.timing == 1, &S);
         if (st != HWPM_OK) return st;
     }
     if (h->host[0] & 4) return HWPM_EBADMATCH;
     const int32_t* start = P.mate;
     if (match) {
-        st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, opt.timing != 0, &S);
+        st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, opt.timing == 1, &S);
         if (st == HWPM_ESINGULAR) {
             // some blocks have no perfect matching: solve the others one by one
             std::vector<int32_t> unm(count);

@@ -23,7 +23,7 @@ enum CounterWord : int {
     kRoundsRun = 5,    // search passes run so far
     kCycles = 6,       // u64 in words 6-7: cycles flipped in all rounds
     kRoundBase = 8,    // per-round words, kSlotWords per slot of the ring
-    kCounterWords = 128,
+    kSpreadBase = 128, // sub-list counters of the wave-per-root hand-off (below)
 };
 
 // Per-round words of one ring slot.
@@ -31,12 +31,23 @@ enum SlotWord : int {
     kCand = 0,         // roots with a Step-C winner
     kApplied = 1,      // cycles flipped
     kRoots = 2,        // roots to search in this round (incremental mode)
-    kMedium = 3,       // roots handed to the wave-per-root search this round
     kHeavy = 4,        // flipped rows whose mate columns are refreshed by the whole grid
     kSlotWords = 8,
 };
 
 __host__ __device__ inline int slot_word(int slot, int w) { return kRoundBase + kSlotWords * slot + w; }
+
+// The roots the tile kernels hand to the wave-per-root kernel go to kSpread
+// sub-lists per round (by block index), each with its own counter in its own
+// 128-byte line: appends from the whole grid would otherwise queue on one
+// counter address.  Sub-list s of a round holds at most `cap` roots, at
+// medium[s * cap ...).
+constexpr int kSpread = 64;
+constexpr int kSpreadStride = 32;  // words between two sub-list counters
+constexpr int kCounterWords = kSpreadBase + kSlots * kSpread * kSpreadStride;
+__host__ __device__ inline int spread_word(int slot, int s) {
+    return kSpreadBase + (slot * kSpread + s) * kSpreadStride;
+}
 
 // Append to a device list whose length is *counter: every active lane of the
 // wave with want set gets its own slot (returned; -1 for the others), and
@@ -105,11 +116,11 @@ struct Work {
     int32_t* flips;     // 4 per flipped cycle: (i, new mate j), (l, new mate c)
     int32_t* dirty;     // n: root must be searched again (incremental mode)
     int32_t* dirty_list;// n: the roots to search next round
-    int32_t* medium;    // n: roots for the wave-per-root search (this round)
+    int32_t* medium;    // n + kSpread * 64: roots for the wave-per-root search (this round), in sub-lists
     int32_t* heavy;     // n: new mate columns of the flipped rows with long lists (this round)
     int32_t* round_stats; // 3 x kMaxRoundStats: candidates, flips, roots searched
     // staging of the bucketed transpose
-    int32_t* colof;     // nnz: column of each CSC entry
+    int32_t* tile_col;  // first column of every pass-1 tile (the column holding its first entry)
     int32_t* tp_row;
     int32_t* tp_col;
     int32_t* tp_pos;

@@ -216,6 +216,8 @@ __global__ void k_apply(Csc A, Work W, int slot, int transposed) {
     const int32_t nc = W.counters[slot_word(slot, kCand)];
     if (blockIdx.x == 0 && threadIdx.x < kSlotWords)
         W.counters[slot_word((slot + 1) % kSlots, threadIdx.x)] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kSpread)
+        W.counters[spread_word((slot + 1) % kSlots, threadIdx.x)] = 0;
     for (int32_t t = blockIdx.x * blockDim.x + threadIdx.x; t < nc; t += gridDim.x * blockDim.x) {
         const int32_t j = W.cand[t];
         const int32_t c = W.best_c[j];
@@ -398,7 +400,7 @@ __global__ void k_mrk_fill(Csc A, Work W) {
 // contiguous runs, filling the per-entry mate columns on the way.  Pass 2
 // gives each bucket one block, which counts its slots in LDS, writes the slot
 // pointers and places every entry (the bucket's output range is small enough
-// to stay in L2).  The column of an entry comes from colof[].
+// to stay in L2).
 constexpr int kTpTile = 4096;     // entries per pass-1 tile (256 threads x 16)
 constexpr int kTpMaxBuckets = 1024;
 constexpr int kTpMaxRows = 8192;  // slots per bucket (LDS counters of pass 2)
@@ -426,27 +428,14 @@ TpPlan tp_plan(int64_t n, int64_t nnz) {
     return P;
 }
 
-// colof[k] = column of entry k: a tile per short column, a block per chunk of
-// a long column.
-template <int T>
-__global__ __launch_bounds__(256) void k_colof_short(Csc A, Work W, int32_t long_threshold) {
-    const int lane = threadIdx.x & (T - 1);
-    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
-    if (tile >= A.n) return;
-    const int64_t lo = A.col_ptr[tile], hi = A.col_ptr[tile + 1];
-    if (hi - lo > long_threshold) return;
-    for (int64_t k = lo + lane; k < hi; k += T) W.colof[k] = (int32_t)tile;
-}
-
-__global__ __launch_bounds__(256) void k_colof_long(Csc A, Work W) {
-    const int32_t total = W.counters[kNumChunks];
-    for (int32_t cid = blockIdx.x; cid < total; cid += gridDim.x) {
-        const int32_t a = W.chunk_col[cid];
-        const int32_t j = W.long_list[a];
-        const int64_t lo = A.col_ptr[j] + (int64_t)(cid - W.chunk_off[a]) * kLongChunk;
-        const int64_t hi0 = A.col_ptr[j + 1];
-        const int64_t hi = (lo + kLongChunk < hi0) ? lo + kLongChunk : hi0;
-        for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) W.colof[k] = j;
+// The column of the first entry of every pass-1 tile: column c owns the
+// tiles whose first entry lies in [col_ptr[c], col_ptr[c+1]).
+__global__ __launch_bounds__(256) void k_tp_tile_cols(Csc A, Work W, int32_t nseg) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < A.n;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t lo = A.col_ptr[c], hi = A.col_ptr[c + 1];
+        for (int64_t t = (lo + kTpTile - 1) / kTpTile; t < nseg && t * kTpTile < hi; ++t)
+            W.tile_col[t] = (int32_t)c;
     }
 }
 
@@ -482,14 +471,16 @@ __global__ __launch_bounds__(256) void k_tp_hist(Csc A, Work W, int rb, int32_t 
 #pragma unroll
     for (int u = 0; u < kTpTile / 256; ++u) {
         const int64_t k = k0 + threadIdx.x + 256 * u;
-        sl[u] = (k < A.nnz) ? A.row_idx[k] : -1;
+        sl[u] = (k < A.nnz) ? __builtin_nontemporal_load(A.row_idx + k) : -1;
     }
+    // the two streams are marked nontemporal so that they do not push the
+    // gathered mate array (n words, read at random) out of L2
 #pragma unroll
     for (int u = 0; u < kTpTile / 256; ++u) {
         const int64_t k = k0 + threadIdx.x + 256 * u;
         if (sl[u] >= 0) {
             sl[u] = W.mr[sl[u]];
-            W.mrk[k] = sl[u];
+            __builtin_nontemporal_store(sl[u], W.mrk + k);
         }
     }
 #pragma unroll
@@ -505,22 +496,59 @@ __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32
                                                     const int64_t* __restrict__ off) {
     __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[kTpMaxBuckets], start[kTpMaxBuckets], base[kTpMaxBuckets];
-    __shared__ int32_t wsum[4];
+    constexpr int U = kTpTile / 256;
+    __shared__ int32_t wsum[4], wmax[4 * U];
     const int32_t seg = blockIdx.x;
+    const int64_t k0 = (int64_t)seg * kTpTile;
+    const int32_t len = (int32_t)((k0 + kTpTile < A.nnz) ? kTpTile : A.nnz - k0);
+    // The column of every entry of the tile: the tile's first column, a mark
+    // at the first entry of each later column that starts inside the tile,
+    // and a running maximum along the tile (columns do not decrease along the
+    // entries; an empty column starts where the next one does and loses).
+    int32_t* mark = s_col;  // free until the placement below
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         hist[b] = 0;
         base[b] = (int32_t)off[(int64_t)b * nseg + seg];
     }
+#pragma unroll
+    for (int u = 0; u < U; ++u) mark[threadIdx.x + 256 * u] = -1;
     __syncthreads();
-    const int64_t k0 = (int64_t)seg * kTpTile;
-    constexpr int U = kTpTile / 256;
+    int32_t cf = W.tile_col[seg];
+    cf = cf < 0 ? 0 : (cf >= A.n ? A.n - 1 : cf);
+    if (threadIdx.x == 0) mark[0] = cf;
+    for (int64_t c = (int64_t)cf + 1 + threadIdx.x; c <= A.n; c += blockDim.x) {
+        const int64_t p = A.col_ptr[c];
+        if (p >= k0 + len) break;  // and so for every later column
+        if (p > k0) atomicMax(&mark[p - k0], (int32_t)c);
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t sl[U], co[U], rk[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = k0 + threadIdx.x + 256 * u;
-        const bool ok = k < A.nnz;
-        sl[u] = ok ? W.mrk[k] : -1;
-        co[u] = ok ? W.colof[k] : -1;
+        sl[u] = (k < A.nnz) ? W.mrk[k] : -1;
+        co[u] = mark[threadIdx.x + 256 * u];
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {  // running max over the wave's part of row u
+            const int32_t v = __shfl_up(co[u], o, 64);
+            if (lane >= o) co[u] = co[u] > v ? co[u] : v;
+        }
+        if (lane == 63) wmax[4 * u + wave] = co[u];
+    }
+    __syncthreads();
+    {
+        // entry x = 256 u + threadIdx.x follows rows 0..u-1 and, in row u, the
+        // waves before this one
+        int32_t pre = -1;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int32_t rp = pre;
+            for (int w = 0; w < wave; ++w) rp = rp > wmax[4 * u + w] ? rp : wmax[4 * u + w];
+            co[u] = co[u] > rp ? co[u] : rp;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) pre = pre > wmax[4 * u + w] ? pre : wmax[4 * u + w];
+        }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u)
@@ -531,7 +559,6 @@ __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32
     const int bb = threadIdx.x * per, be = (bb + per < nb) ? bb + per : nb;
     int32_t run = 0;
     for (int b = bb; b < be; ++b) run += hist[b];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     int32_t incl = run;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -557,7 +584,6 @@ __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32
         }
     }
     __syncthreads();
-    const int32_t len = (int32_t)((k0 + kTpTile < A.nnz) ? kTpTile : A.nnz - k0);
     for (int32_t e = threadIdx.x; e < len; e += blockDim.x) {
         const int32_t slot = s_slot[e];
         const int32_t b = slot >> rb;
@@ -776,14 +802,11 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     }
 }
 
-hipError_t launch_transpose_buckets(const Csc& A, const Work& W, int32_t long_threshold,
-                                    bool has_long, bool positions, hipStream_t s, int cus) {
+hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions, hipStream_t s, int cus) {
     const TpPlan P = tp_plan(A.n, A.nnz);
     const int32_t nb = (int32_t)P.nb, nseg = (int32_t)P.nseg;
     const int64_t m = P.nb * P.nseg;
-    const unsigned tiles = (unsigned)(((int64_t)A.n * 16 + 255) / 256);
-    hipLaunchKernelGGL(k_colof_short<16>, dim3(tiles), dim3(256), 0, s, A, W, long_threshold);
-    if (has_long) hipLaunchKernelGGL(k_colof_long, dim3(cus * 8), dim3(256), 0, s, A, W);
+    hipLaunchKernelGGL(k_tp_tile_cols, dim3(cus * 8), dim3(256), 0, s, A, W, nseg);
     hipLaunchKernelGGL(k_tp_hist, dim3(nseg), dim3(256), 0, s, A, W, P.rb, nb, nseg, W.tp_cnt);
     const int64_t sb = (m + 2047) / 2048;
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)sb), dim3(256), 0, s, W.tp_cnt, m, W.tp_off, W.tp_sums);
@@ -809,7 +832,7 @@ hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold,
     hipError_t e;
     if (tp_plan(A.n, A.nnz).ok) {
         // also fills mrk
-        return launch_transpose_buckets(A, W, long_threshold, has_long, positions, s, cus);
+        return launch_transpose_buckets(A, W, positions, s, cus);
     } else {
         // very large matrices: counting sort with global atomics
         if ((e = hipMemsetAsync(W.rowcnt, 0, (size_t)n * sizeof(int32_t), s)) != hipSuccess) return e;
@@ -833,11 +856,11 @@ hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold,
 // After the flips of a round: the entries of every row whose mate changed get
 // the new mate column (one block per flipped row; a row with more than
 // kHeavyRow entries is left to k_mrk_update_heavy, which spreads each such
-// row over the whole grid).  In incremental mode the columns of those entries
-// are marked for the next round: a root's Step-C result can change only if
-// its own mate changed or one of its rows got a new mate (every value its
-// gains read is otherwise the same), and the flipped columns themselves
-// appear in the lists of their new rows.
+// row over a row of blocks, eight rows at a time).  In incremental mode the
+// columns of those entries are marked for the next round: a root's Step-C
+// result can change only if its own mate changed or one of its rows got a
+// new mate (every value its gains read is otherwise the same), and the
+// flipped columns themselves appear in the lists of their new rows.
 constexpr int32_t kHeavyRow = 4096;
 
 __device__ __forceinline__ void refresh_entry(const Csc& A, const Work& W, int64_t x, int32_t m, int32_t row,
@@ -877,7 +900,8 @@ __global__ __launch_bounds__(256) void k_mrk_update_heavy(Csc A, Work W, int slo
     const int32_t nh = W.counters[slot_word(slot, kHeavy)];
     const int next = (slot + 1) % kSlots;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int32_t h = 0; h < nh; ++h) {
+    // gridDim.y rows at a time, each over a row of blocks
+    for (int32_t h = blockIdx.y; h < nh; h += gridDim.y) {
         const int32_t m = W.heavy[h];
         const int64_t b = W.rstart[m], e = b + W.rlen[m];
         const int32_t row = W.mc[m];
@@ -911,7 +935,8 @@ hipError_t launch_round_end(const Work& W, int slot, int round, bool listed, int
 
 hipError_t launch_mrk_update(const Csc& A, const Work& W, int slot, bool incremental, hipStream_t s, int cus) {
     hipLaunchKernelGGL(k_mrk_update, dim3(cus * 4), dim3(256), 0, s, A, W, slot, incremental ? 1 : 0);
-    hipLaunchKernelGGL(k_mrk_update_heavy, dim3(cus * 4), dim3(256), 0, s, A, W, slot, incremental ? 1 : 0);
+    hipLaunchKernelGGL(k_mrk_update_heavy, dim3(cus / 2 > 0 ? cus / 2 : 1, 8), dim3(256), 0, s, A, W, slot,
+                       incremental ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -1028,13 +1053,13 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.flips = (int32_t*)take(N * 4 * 4 / 2 + 16);
     W.dirty = (int32_t*)take(N * 4);
     W.dirty_list = (int32_t*)take(N * 4);
-    W.medium = (int32_t*)take(N * 4);
+    W.medium = (int32_t*)take((N + kSpread * 64) * 4);
     W.heavy = (int32_t*)take(N * 4);
     W.round_stats = (int32_t*)take(3 * kMaxRoundStats * 4);
     const TpPlan P = tp_plan(n, nnz);
     const size_t tpm = P.ok ? (size_t)(P.nb * P.nseg) : 0;
     const size_t tpz = P.ok ? Z : 0;
-    W.colof = (int32_t*)take(tpz * 4);
+    W.tile_col = (int32_t*)take(P.ok ? (size_t)(P.nseg + 1) * 4 : 0);
     W.tp_row = (int32_t*)take(tpz * 4);
     W.tp_col = (int32_t*)take(tpz * 4);
     W.tp_pos = (int32_t*)take(tpz * 4);

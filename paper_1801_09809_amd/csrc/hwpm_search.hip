@@ -236,7 +236,8 @@ __global__ __launch_bounds__(256) void k_search_rows(Csc A, Work W, int32_t long
 // with a longer column or row list go to the wave-per-root kernel.
 template <int T, int E>
 __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t long_threshold,
-                                                      int slot, const int32_t* __restrict__ roots) {
+                                                      int slot, const int32_t* __restrict__ roots,
+                                                      int32_t cap) {
     if (round_over(W)) return;
     const int lane = threadIdx.x & (T - 1);
     // roots: this round's list (its length on the device; the grid covers
@@ -257,9 +258,10 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
         const int32_t rlen = W.rlen[j];
         // a root too long for the tile goes to the wave-per-root kernel
         const bool handoff = len > T * E || rlen > T * E;
-        const int32_t q = wave_append(&W.counters[slot_word(slot, kMedium)], handoff && lane == 0);
+        const int sub = blockIdx.x & (kSpread - 1);
+        const int32_t q = wave_append(&W.counters[spread_word(slot, sub)], handoff && lane == 0);
         if (handoff) {
-            if (lane == 0) W.medium[q] = j;
+            if (lane == 0) W.medium[(int64_t)sub * cap + q] = j;
             return;  // tile-uniform
         }
         {
@@ -321,17 +323,31 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-__global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot) {
+__global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot, int32_t cap) {
     __shared__ int32_t keys[4][kHashSlots];
     __shared__ int32_t vals[4][kHashSlots];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     int32_t* hk = keys[wv];
     int32_t* hv = vals[wv];
     if (round_over(W)) return;
-    const int32_t count = W.counters[slot_word(slot, kMedium)];
     const int32_t waves = gridDim.x * 4;
-    for (int32_t q = blockIdx.x * 4 + wv; q < count; q += waves) {  // wave-uniform
-        const int32_t j = W.medium[q];
+    const int32_t wid = blockIdx.x * 4 + wv;
+    // the sub-lists read as one list (sub-list order, then position), dealt
+    // round-robin to the waves: lane s holds the number of roots in
+    // sub-lists 0..s, so the sub-list of a list index is one ballot
+    static_assert(kSpread == 64, "one sub-list per lane");
+    const int32_t len_s = W.counters[spread_word(slot, lane)];
+    int32_t incl = len_s;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    const int32_t total = __shfl(incl, 63, 64);
+    for (int32_t item = wid; item < total; item += waves) {  // wave-uniform
+        const int sub = (int)__popcll(__ballot(incl <= item));
+        const int32_t at = item - __shfl(incl - len_s, sub, 64);
+        const int32_t j = W.medium[(int64_t)sub * cap + at];
         const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
         const int32_t mj = W.mc[j];
         const double wmj = W.wm[j];
@@ -412,7 +428,7 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot) 
 __device__ __forceinline__ int4 ld4(const int32_t* p) { return *reinterpret_cast<const int4*>(p); }
 
 __global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_threshold, int slot,
-                                                    const int32_t* __restrict__ roots) {
+                                                    const int32_t* __restrict__ roots, int32_t cap) {
     constexpr int T = 4, E = 8;
     if (round_over(W)) return;
     const int lane = threadIdx.x & 3;
@@ -433,9 +449,10 @@ __global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_
         const int64_t cb = lo & ~(int64_t)3, rb = rs & ~(int64_t)3;
         // a segment that does not fit its window goes to the wave-per-root kernel
         const bool handoff = !(hi <= cb + 32 && rs + rlen <= rb + 32 && cb + 32 <= A.nnz);
-        const int32_t q = wave_append(&W.counters[slot_word(slot, kMedium)], handoff && lane == 0);
+        const int sub = blockIdx.x & (kSpread - 1);
+        const int32_t q = wave_append(&W.counters[spread_word(slot, sub)], handoff && lane == 0);
         if (handoff) {
-            if (lane == 0) W.medium[q] = j;
+            if (lane == 0) W.medium[(int64_t)sub * cap + q] = j;
             return;  // tile-uniform
         }
         {
@@ -500,16 +517,21 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
     else                                                                                    \
         hipLaunchKernelGGL(k_search_short<TW>, dim3(blocks), dim3(256), 0, s, A, W,         \
                            long_threshold, slot);
+    // hand-off sub-list capacity: the roots of the blocks that share a
+    // sub-list (kSpread sub-lists hold at most n + 4095 roots in all)
+    int32_t cap = 0;
     if (probe == 4) {
         const int64_t vall = ((int64_t)A.n * 4 + 255) / 256;
         const unsigned vblocks = (unsigned)(vall > 0 ? vall : 1);
-        hipLaunchKernelGGL(k_search_vec, dim3(vblocks), dim3(256), 0, s, A, W, long_threshold, slot, roots);
+        cap = (int32_t)((vblocks + kSpread - 1) / kSpread * (256 / 4));
+        hipLaunchKernelGGL(k_search_vec, dim3(vblocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap);
     } else if (probe == 3) {
+        cap = (int32_t)((blocks + kSpread - 1) / kSpread * (256 / tile_width));
         switch (tile_width) {
-            case 4: hipLaunchKernelGGL((k_search_chunk<4, 8>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots); break;
-            case 8: hipLaunchKernelGGL((k_search_chunk<8, 4>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots); break;
-            case 16: hipLaunchKernelGGL((k_search_chunk<16, 2>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots); break;
-            case 32: hipLaunchKernelGGL((k_search_chunk<32, 1>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots); break;
+            case 4: hipLaunchKernelGGL((k_search_chunk<4, 8>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+            case 8: hipLaunchKernelGGL((k_search_chunk<8, 4>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+            case 16: hipLaunchKernelGGL((k_search_chunk<16, 2>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+            case 32: hipLaunchKernelGGL((k_search_chunk<32, 1>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
             default: return hipErrorInvalidValue;
         }
     } else switch (tile_width) {
@@ -521,7 +543,7 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
         default: return hipErrorInvalidValue;
     }
 #undef HWPM_SEARCH
-    if (probe >= 3) hipLaunchKernelGGL(k_search_medium, dim3(cus * 8), dim3(256), 0, s, A, W, slot);
+    if (probe >= 3) hipLaunchKernelGGL(k_search_medium, dim3(cus * 8), dim3(256), 0, s, A, W, slot, cap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !has_long) return e;
     const int only_dirty = (listed && incremental) ? 1 : 0;

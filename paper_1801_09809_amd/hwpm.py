@@ -468,7 +468,7 @@ class Solver:
         opt = hwpm_default_options()
         opt.max_rounds = int(max_rounds)
         opt.check_csc = int(bool(check_csc))
-        opt.timing = int(bool(timing))
+        opt.timing = int(timing)  # False/True -> 0/1; 2: search stage only
         opt.tile_width = int(tile_width)
         opt.probe = int(probe)
         opt.mcm_plain = int(bool(mcm_plain))
@@ -545,7 +545,7 @@ class Solver:
 
     def improve(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
                 mate_in: torch.Tensor, perm_out: torch.Tensor | None = None, max_rounds: int = 0,
-                check_csc: bool = True, timing: bool = False, tile_width: int = 0,
+                check_csc: bool = True, timing: int = 0, tile_width: int = 0,
                 probe: int = 0, full_search: bool = False) -> ImproveResult:
         n = col_ptr.numel() - 1
         nnz = row_idx.numel()

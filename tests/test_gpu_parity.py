@@ -188,6 +188,31 @@ def test_aliasing_and_determinism(solver):
         assert res.total == ref.total
 
 
+@pytest.mark.parametrize("probe", [1, 3, 5])
+def test_timing_levels(solver, probe):
+    """Timing never changes the result; level 2 fills only the search-stage
+    times, level 1 every stage; other levels are rejected."""
+    from paper_1801_09809_amd import hwpm
+    wl = small_random(20001, 9, 33)
+    ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
+    by = {}
+    for level in (0, 1, 2):
+        gpu = gpu_improve(solver, wl, timing=level, probe=probe, full_search=True)
+        assert_same(wl, gpu, ref)
+        by[level] = gpu[2]
+    assert by[0]["ms_search"] == 0.0 and by[0]["ms_setup"] == 0.0
+    for level in (1, 2):
+        st = by[level]
+        assert st["ms_search"] > 0.0
+        assert st["ms_search_first"] > 0.0
+        assert all(x > 0.0 for x in st["round_ms_search"][:st["rounds"]])
+        assert abs(sum(st["round_ms_search"][:st["rounds"]]) - st["ms_search"]) <= 1e-3 * st["ms_search"] + 1e-4
+    assert by[1]["ms_setup"] > 0.0 and by[1]["ms_resolve"] > 0.0 and by[1]["ms_apply"] > 0.0
+    assert by[2]["ms_setup"] == 0.0 and by[2]["ms_resolve"] == 0.0 and by[2]["ms_apply"] == 0.0
+    for bad in (-1, 3):
+        _expect(solver, hwpm.HWPM_EINVAL, wl.col_ptr, wl.row_idx, wl.w, wl.planted, timing=bad)
+
+
 # ---------------------------------------------------------------------------
 # error paths (forced from the host; the validation kernels bound every access)
 

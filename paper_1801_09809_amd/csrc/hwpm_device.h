@@ -162,5 +162,15 @@ __device__ __forceinline__ uint32_t hash_col(int32_t c, uint32_t mask) {
     return ((uint32_t)c * 0x9E3779B1u >> 12) & mask;
 }
 
+// Lookup in an LDS open-addressing table (keys hk, values hv, empty key -1,
+// size mask + 1, linear probing): the value stored with key c, else -1.
+__device__ __forceinline__ int32_t hash_find(const int32_t* hk, const int32_t* hv, int32_t c, uint32_t mask) {
+    for (uint32_t h = hash_col(c, mask);; h = (h + 1) & mask) {
+        const int32_t key = hk[h];
+        if (key == c) return hv[h];
+        if (key == -1) return -1;
+    }
+}
+
 
 }  // namespace hwpm

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(256) void k_search_short(Csc A, Work W, int32_t lon
 // searches row m_j in column m_i.
 constexpr int kLongHashMax = 2048;
 constexpr int kLongHashSlots = 4096;
+constexpr int kLongPre = kLongChunk / 256;  // chunk entries per thread
 
 __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dirty, int transposed) {
     __shared__ double sg[4];
@@ -62,6 +63,15 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
         Cand b{0.0, INT32_MAX, -1, -1, -1};
         const int32_t rlen = transposed ? W.rlen[j] : INT32_MAX;
         if (rlen <= kLongHashMax) {
+            // the chunk's entries (kLongPre per thread) are loaded before the
+            // table is built, so that both loads are in flight together
+            int32_t iq[kLongPre], mq[kLongPre];
+#pragma unroll
+            for (int q = 0; q < kLongPre; ++q) {
+                const int64_t k = lo + threadIdx.x + 256 * q;
+                iq[q] = (k < hi) ? A.row_idx[k] : -1;
+                mq[q] = (k < hi) ? W.mrk[k] : -1;
+            }
             const int64_t rs = W.rstart[j];
             uint32_t size = 256;
             while ((int32_t)size < 2 * rlen) size <<= 1;
@@ -75,22 +85,13 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
                 hv[h] = x;
             }
             __syncthreads();
-            for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) {
-                const int32_t i = A.row_idx[k];
-                if (i <= mj) continue;
-                const int32_t mi = W.mrk[k];
-                uint32_t h = hash_col(mi, mask);
-                int32_t qx = -1;
-                for (;;) {
-                    const int32_t key = hk[h];
-                    if (key == mi) {
-                        qx = hv[h];
-                        break;
-                    }
-                    if (key == -1) break;
-                    h = (h + 1) & mask;
-                }
+#pragma unroll
+            for (int q = 0; q < kLongPre; ++q) {
+                const int32_t i = iq[q], mi = mq[q];
+                if (i <= mj) continue;  // also the slots past the chunk (i = -1)
+                const int32_t qx = hash_find(hk, hv, mi, mask);
                 if (qx < 0) continue;
+                const int64_t k = lo + threadIdx.x + 256 * q;
                 const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + qx] : find_row(A.col_ptr, A.row_idx, mi, mj);
                 const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
                 if (g > 0.0 && better(g, i, b.g, b.i)) {
@@ -317,6 +318,7 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
 // row m_j in column m_i.  The 64 lanes stride over the column.
 constexpr int kHashMax = 512;       // row-list entries a wave hashes
 constexpr int kHashSlots = 1024;    // table size per wave (load factor <= 1/2)
+constexpr int kHashPre = 4;         // column entries per lane loaded up front
 
 __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -355,6 +357,16 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot, 
         const int32_t rlen = W.rlen[j];
         Cand b{0.0, INT32_MAX, -1, -1, -1};
         if (rlen <= kHashMax) {
+            // the column's entries (at most 256: longer columns are split)
+            // are loaded before the table is built, so that both loads are in
+            // flight together
+            int32_t iq[kHashPre], mq[kHashPre];
+#pragma unroll
+            for (int q = 0; q < kHashPre; ++q) {
+                const int64_t k = lo + lane + 64 * q;
+                iq[q] = (k < hi) ? A.row_idx[k] : -1;
+                mq[q] = (k < hi) ? W.mrk[k] : -1;
+            }
             uint32_t size = 64;
             while ((int32_t)size < 2 * rlen) size <<= 1;
             const uint32_t mask = size - 1;
@@ -368,28 +380,20 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot, 
                 hv[h] = x;
             }
             wave_lds_sync();
-            for (int64_t k = lo + lane; k < hi; k += 64) {
-                const int32_t i = A.row_idx[k];
-                if (i <= mj) continue;
-                const int32_t mi = W.mrk[k];
-                uint32_t h = hash_col(mi, mask);
-                int32_t qx = -1;
-                for (;;) {
-                    const int32_t key = hk[h];
-                    if (key == mi) {
-                        qx = hv[h];
-                        break;
-                    }
-                    if (key == -1) break;
-                    h = (h + 1) & mask;
-                }
-                if (qx < 0) continue;
+            auto probe = [&](int64_t k, int32_t i, int32_t mi) {
+                if (i <= mj) return;
+                const int32_t qx = hash_find(hk, hv, mi, mask);
+                if (qx < 0) return;
                 const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + qx] : find_row(A.col_ptr, A.row_idx, mi, mj);
                 const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
                 if (g > 0.0 && better(g, i, b.g, b.i)) {
                     b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
                 }
-            }
+            };
+#pragma unroll
+            for (int q = 0; q < kHashPre; ++q)
+                if (iq[q] >= 0) probe(lo + lane + 64 * q, iq[q], mq[q]);
+            for (int64_t k = lo + 64 * kHashPre + lane; k < hi; k += 64) probe(k, A.row_idx[k], W.mrk[k]);
         } else {
             // four entries per lane, their binary searches in lockstep
             for (int64_t k0 = lo + lane; k0 < hi; k0 += 4 * 64) {

@@ -2,6 +2,7 @@
 folder, and derive the HBM traffic of a kernel from two counter passes.
 
     python -m paper_1801_09809_amd.profsummary trace RESULTS.db --command "..."
+    python -m paper_1801_09809_amd.profsummary pmc --fetch FETCH.db --write WRITE.db --copy-bytes N
     python -m paper_1801_09809_amd.profsummary traffic --fetch FETCH.db --write WRITE.db \
         --kernel k_search_chunk,k_search_medium --name search_stage --copy-bytes N \
         --source csrc/hwpm_search.hip,csrc/hwpm_device.h,csrc/hwpm_internal.h \
@@ -137,6 +138,49 @@ def cmd_traffic(args) -> int:
     return 0
 
 
+def _copy_factor(vals, copy_bytes):
+    cv = sorted((v for n, v in vals if n.startswith(COPY_KERNEL)), reverse=True)[:3]
+    if not cv:
+        raise SystemExit(f"no {COPY_KERNEL} dispatch to calibrate with")
+    copy_kib = sum(cv) / len(cv)
+    return copy_kib, (copy_bytes / 1024.0) / copy_kib
+
+
+def cmd_pmc(args) -> int:
+    """Per-kernel HBM traffic of every kernel in two counter passes, raw and
+    calibrated, averaged over each kernel's dispatches (MB = 10^6 bytes)."""
+    fv = dispatch_values(sqlite3.connect(args.fetch), "FETCH_SIZE")
+    wv = dispatch_values(sqlite3.connect(args.write), "WRITE_SIZE")
+    f_copy, f_fac = _copy_factor(fv, args.copy_bytes)
+    w_copy, w_fac = _copy_factor(wv, args.copy_bytes)
+    fk, wk = defaultdict(list), defaultdict(list)
+    for n, v in fv:
+        fk[n].append(v)
+    for n, v in wv:
+        wk[n].append(v)
+    if args.command_fetch:
+        print(f"command (FETCH_SIZE pass): {args.command_fetch}")
+    if args.command_write:
+        print(f"command (WRITE_SIZE pass): {args.command_write}")
+    mib = args.copy_bytes / 1048576
+    print(f"calibration: three device copies of {mib:.0f} MiB read FETCH_SIZE {f_copy:.0f} KiB and "
+          f"WRITE_SIZE {w_copy:.0f} KiB each,")
+    print(f"so counted KiB are scaled by {f_fac:.4f} (reads) and {w_fac:.4f} (writes); values below are "
+          "per dispatch, averaged over dispatches.")
+    print("note: a kernel's WRITE_SIZE also counts lines the previous kernel left dirty in the caches, "
+          "so writes are attributed loosely.\n")
+    print(f"{'fetch_MB':>10} {'write_MB':>10} {'calib_read_MB':>14} {'calib_write_MB':>15} {'n':>4}  kernel")
+    rows = []
+    for n in set(fk) | set(wk):
+        f = sum(fk[n]) / len(fk[n]) if fk[n] else 0.0
+        w = sum(wk[n]) / len(wk[n]) if wk[n] else 0.0
+        rows.append((f * f_fac + w * w_fac, n, f, w, max(len(fk[n]), len(wk[n]))))
+    for _, n, f, w, cnt in sorted(rows, reverse=True)[: args.top]:
+        print(f"{f * 1.024e-3:10.2f} {w * 1.024e-3:10.2f} {f * f_fac * 1.024e-3:14.2f} "
+              f"{w * w_fac * 1.024e-3:15.2f} {cnt:4d}  {n[:100]}")
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -156,8 +200,15 @@ def main(argv=None) -> int:
     r.add_argument("--workload", required=True, help="name of the workload the passes ran on")
     r.add_argument("--probe", type=int, required=True, help="the probe the passes ran with")
     r.add_argument("--command", default="")
+    m = sub.add_parser("pmc")
+    m.add_argument("--fetch", required=True, help="database of the FETCH_SIZE pass")
+    m.add_argument("--write", required=True, help="database of the WRITE_SIZE pass")
+    m.add_argument("--copy-bytes", type=int, required=True, help="bytes of each calibration copy")
+    m.add_argument("--command-fetch", default="")
+    m.add_argument("--command-write", default="")
+    m.add_argument("--top", type=int, default=25)
     args = ap.parse_args(argv)
-    return cmd_trace(args) if args.cmd == "trace" else cmd_traffic(args)
+    return {"trace": cmd_trace, "traffic": cmd_traffic, "pmc": cmd_pmc}[args.cmd](args)
 
 
 if __name__ == "__main__":

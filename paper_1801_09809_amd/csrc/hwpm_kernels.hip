@@ -66,6 +66,39 @@ hipError_t launch_check_csc(const Csc& A, const Work& W, hipStream_t s, int cus)
 // Set-up: replicate the mates and matched weights (the initial broadcast of
 // Algorithm 2), validate the matching, list the long columns.
 
+// find_row with the final window's nine reads issued together: each index
+// is clamped to the column's last entry (to entry 0 for an empty column, so
+// the matrix must hold at least one entry) and only the slots inside the
+// column can hit.  One thread per column here, so the nine registers are
+// cheap; the search kernels keep find_row.
+__device__ __forceinline__ int64_t find_row_window(const int64_t* __restrict__ col_ptr,
+                                                   const int32_t* __restrict__ row_idx, int32_t c,
+                                                   int32_t r) {
+    int64_t lo = col_ptr[c];
+    const int64_t end = col_ptr[c + 1];
+    int64_t len = end - lo;
+    while (len > 8) {
+        const int64_t half = len >> 1;
+        if (row_idx[lo + half] < r) {
+            lo += half + 1;
+            len -= half + 1;
+        } else {
+            len = half;
+        }
+    }
+    int32_t v[9];
+#pragma unroll
+    for (int q = 0; q <= 8; ++q) {
+        const int64_t pos = lo + q;
+        v[q] = row_idx[pos < end ? pos : (end > 0 ? end - 1 : 0)];
+    }
+    int64_t hit = -1;
+#pragma unroll
+    for (int q = 0; q <= 8; ++q)
+        if (q <= len && lo + q < end && v[q] == r) hit = lo + q;
+    return hit;
+}
+
 __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
                              int32_t long_threshold) {
     for (int64_t jj = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; jj < A.n;
@@ -85,7 +118,7 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
         }
         W.mr[r] = j;  // a row claimed twice keeps one writer: k_check_match sees the other
         W.mc[j] = r;
-        const int64_t p = find_row(A.col_ptr, A.row_idx, j, r);
+        const int64_t p = find_row_window(A.col_ptr, A.row_idx, j, r);
         if (p < 0) {
             atomicOr(&W.counters[kErrMatch], 4);
             W.wm[j] = 0.0;
@@ -462,30 +495,37 @@ __device__ __forceinline__ void wave_scan128(int32_t* cnt) {
 // bucket-major.
 __global__ __launch_bounds__(256) void k_tp_hist(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
                                                  int32_t* __restrict__ cnt) {
+    constexpr int U = kTpTile / 256;
     __shared__ int32_t hist[kTpMaxBuckets];
     for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int32_t seg = blockIdx.x;
     const int64_t k0 = (int64_t)seg * kTpTile;
-    int32_t sl[kTpTile / 256];
+    if (A.nnz > 0) {  // block-uniform
+        // Loads first, with indices clamped to the last entry, so that the U
+        // row-index loads and then the U gathers are each in flight
+        // together; the stores and counts of the entries past the end are
+        // skipped afterwards.  The two streams are marked nontemporal so
+        // that they do not push the gathered mate array (n words, read at
+        // random) out of L2.
+        const int64_t last = A.nnz - 1;
+        int32_t sl[U];
 #pragma unroll
-    for (int u = 0; u < kTpTile / 256; ++u) {
-        const int64_t k = k0 + threadIdx.x + 256 * u;
-        sl[u] = (k < A.nnz) ? __builtin_nontemporal_load(A.row_idx + k) : -1;
-    }
-    // the two streams are marked nontemporal so that they do not push the
-    // gathered mate array (n words, read at random) out of L2
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = k0 + threadIdx.x + 256 * u;
+            sl[u] = __builtin_nontemporal_load(A.row_idx + (k < A.nnz ? k : last));
+        }
 #pragma unroll
-    for (int u = 0; u < kTpTile / 256; ++u) {
-        const int64_t k = k0 + threadIdx.x + 256 * u;
-        if (sl[u] >= 0) {
-            sl[u] = W.mr[sl[u]];
-            __builtin_nontemporal_store(sl[u], W.mrk + k);
+        for (int u = 0; u < U; ++u) sl[u] = W.mr[sl[u]];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = k0 + threadIdx.x + 256 * u;
+            if (k < A.nnz) {
+                __builtin_nontemporal_store(sl[u], W.mrk + k);
+                atomicAdd(&hist[sl[u] >> rb], 1);
+            }
         }
     }
-#pragma unroll
-    for (int u = 0; u < kTpTile / 256; ++u)
-        if (sl[u] >= 0) atomicAdd(&hist[sl[u] >> rb], 1);
     __syncthreads();
     for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[(int64_t)b * nseg + seg] = hist[b];
 }
@@ -612,10 +652,18 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
     const int t = threadIdx.x;
     if (t < kTpSub) hist[t] = 0;
     __syncthreads();
-    for (int64_t eb = e0; eb < e1; eb += blockDim.x) {  // uniform trip count
-        const int64_t e = eb + t;
-        const bool ok = e < e1;
-        if (ok) atomicAdd(&hist[(W.tp_row[e] - r0) >> sb], 1);
+    // loads first (four per thread, indices clamped into the bucket), then
+    // the counts: the loads of a pass are in flight together
+    for (int64_t eb = e0; eb < e1; eb += 4 * (int64_t)blockDim.x) {  // uniform trip count
+        int32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t e = eb + t + (int64_t)blockDim.x * u;
+            v[u] = W.tp_row[e < e1 ? e : e1 - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (eb + t + (int64_t)blockDim.x * u < e1) atomicAdd(&hist[(v[u] - r0) >> sb], 1);
     }
     __syncthreads();
     if (t < 64) {  // one wave scans the 64 sub-bucket counts
@@ -637,12 +685,19 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
         __syncthreads();
         int32_t sl[4], co[4], ps[4], rk[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 4; ++u) {  // loads first, indices clamped into the tile
             const int32_t x = t + 1024 * u;
-            sl[u] = (x < len) ? W.tp_row[t0 + x] : -1;
-            co[u] = (x < len) ? W.tp_col[t0 + x] : 0;
-            ps[u] = (POS && x < len) ? W.tp_pos[t0 + x] : 0;
-            if (sl[u] >= 0) rk[u] = atomicAdd(&hist[(sl[u] - r0) >> sb], 1);
+            const int64_t xc = t0 + (x < len ? x : len - 1);
+            sl[u] = W.tp_row[xc];
+            co[u] = W.tp_col[xc];
+            ps[u] = POS ? W.tp_pos[xc] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (t + 1024 * u < len)
+                rk[u] = atomicAdd(&hist[(sl[u] - r0) >> sb], 1);
+            else
+                sl[u] = -1;
         }
         __syncthreads();
         if (t < 64) {
@@ -708,17 +763,19 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
 #pragma unroll
     for (int u = 0; u < U; ++u) rk[u] = -1;
     for (int64_t c0 = 0; c0 < len; c0 += kPlaceTile) {  // counts (uniform trip count)
+        // loads first (indices clamped into the sub-bucket), then the counts
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t x = c0 + t + 256 * u;
-            const bool ok = x < len;
-            key[u] = ok ? (int32_t)(W.tp_row2[e0 + x] - s0) : 0;
+            const int64_t xc = e0 + (x < len ? x : len - 1);
+            key[u] = (int32_t)(W.tp_row2[xc] - s0);
             if (one_tile) {
-                col[u] = ok ? W.tp_col2[e0 + x] : 0;
-                pos[u] = (POS && ok) ? W.tp_pos2[e0 + x] : 0;
+                col[u] = W.tp_col2[xc];
+                pos[u] = POS ? W.tp_pos2[xc] : 0;
             }
-            if (ok) rk[u] = atomicAdd(&rc[key[u]], 1);
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) rk[u] = (c0 + t + 256 * u < len) ? atomicAdd(&rc[key[u]], 1) : -1;
     }
     __syncthreads();
     if (t < 64) {  // slot pointers; rc becomes the exclusive starts
@@ -767,14 +824,15 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
         if (t < NS) tc[t] = 0;
         __syncthreads();
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < U; ++u) {  // loads first, indices clamped into the tile
             const int32_t x = t + 256 * u;
-            const bool ok = x < tl;
-            key[u] = ok ? (int32_t)(W.tp_row2[e0 + c0 + x] - s0) : 0;
-            col[u] = ok ? W.tp_col2[e0 + c0 + x] : 0;
-            pos[u] = (POS && ok) ? W.tp_pos2[e0 + c0 + x] : 0;
-            rk[u] = ok ? atomicAdd(&tc[key[u]], 1) : -1;
+            const int64_t xc = e0 + c0 + (x < tl ? x : tl - 1);
+            key[u] = (int32_t)(W.tp_row2[xc] - s0);
+            col[u] = W.tp_col2[xc];
+            pos[u] = POS ? W.tp_pos2[xc] : 0;
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) rk[u] = (t + 256 * u < tl) ? atomicAdd(&tc[key[u]], 1) : -1;
         __syncthreads();
         if (t < NS) ts[t] = tc[t];
         __syncthreads();

@@ -166,6 +166,26 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
         }
         pend_nb = 0;
     };
+    // 4. outputs: the total weight, the permutation, the per-round
+    // statistics and the cycle count, read back into the pinned buffer
+    auto queue_outputs = [&](const int32_t* gate) -> int {
+        if (timing) HIP_TRY(hipEventRecord(ev[6], s));
+        HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[0], s, gate));
+        if (gate)
+            HIP_TRY(launch_copy_gated(W.mc, perm_out, n, gate, s, h->cus));
+        else
+            HIP_TRY(hipMemcpyAsync(perm_out, W.mc, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+        if (BP) {
+            HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_total, s, h->cus));
+            HIP_TRY(launch_unpack(*BP, W.mc, s, h->cus));
+        }
+        HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h->host + kHostRounds, W.round_stats, 3 * kMaxRoundStats * sizeof(int32_t),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(h->host + kHostScalar + 2, W.counters + kCycles, 8, hipMemcpyDeviceToHost, s));
+        if (timing) HIP_TRY(hipEventRecord(ev[7], s));
+        return HWPM_OK;
+    };
     for (;;) {
         int32_t nb = batch;
         if (opt.max_rounds > 0 && opt.max_rounds - round < nb) nb = opt.max_rounds - round;
@@ -191,6 +211,13 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
         }
         round += nb;
         ++batches;
+        // single solves queue the output stage behind every batch, gated on
+        // the device's done flag: the batch that ends the rounds then needs
+        // no further host round trip (for the others it does nothing)
+        if (!BP) {
+            const int st = queue_outputs(W.counters + kDone);
+            if (st != HWPM_OK) return st;
+        }
         HIP_TRY(hipMemcpyAsync(h->host, W.counters + kDone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         if (tsearch) read_round_events();  // the previous batch's, while this one runs
         HIP_TRY(hipStreamSynchronize(s));
@@ -210,29 +237,19 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     S.rounds = done ? rounds_run : round;
     static_assert(kMaxRoundStats == HWPM_MAX_ROUND_STATS, "round statistics sizes");
     const int32_t n_stats = S.rounds < kMaxRoundStats ? S.rounds : kMaxRoundStats;
-    // per-round statistics and the cycle count, into the pinned buffer
-    if (n_stats > 0)
-        HIP_TRY(hipMemcpyAsync(h->host + kHostRounds, W.round_stats, 3 * kMaxRoundStats * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h->host + kHostScalar + 2, W.counters + kCycles, 8, hipMemcpyDeviceToHost, s));
-
-    // 4. outputs
-    if (timing) HIP_TRY(hipEventRecord(ev[6], s));
-    HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[0], s));
-    HIP_TRY(hipMemcpyAsync(perm_out, W.mc, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
-    if (BP) {
-        HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_total, s, h->cus));
-        HIP_TRY(launch_unpack(*BP, W.mc, s, h->cus));
+    if (BP || !done) {  // the output stage has not run yet (batches, or the round cap)
+        const int st = queue_outputs(nullptr);
+        if (st != HWPM_OK) return st;
+        if (tsearch) read_round_events();  // while the output stage runs
+        HIP_TRY(hipStreamSynchronize(s));
+    } else if (tsearch) {
+        read_round_events();
     }
-    HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
-    if (timing) HIP_TRY(hipEventRecord(ev[7], s));
-    if (tsearch) read_round_events();  // while the output stage runs
     if (timing) {
         S.ms_setup = elapsed(ev[0], ev[1]);
         if (transposed) S.ms_transpose = elapsed(ev[2], ev[3]);
+        S.ms_final = elapsed(ev[6], ev[7]);
     }
-    HIP_TRY(hipStreamSynchronize(s));
-    if (timing) S.ms_final = elapsed(ev[6], ev[7]);
     unsigned long long cycles = 0;
     memcpy(&cycles, h->host + kHostScalar + 2, sizeof(cycles));
     S.cycles_applied = (int64_t)cycles;

@@ -230,7 +230,11 @@ hipError_t launch_mrk_update(const Csc& A, const Work& W, int slot, bool increme
 hipError_t launch_resolve(const Work& W, int slot, hipStream_t s, int cus);
 hipError_t launch_apply(const Csc& A, const Work& W, int slot, bool transposed, hipStream_t s,
                         int cus);
-hipError_t launch_tree_sum(const double* x, int64_t m, const Work& W, double* out, hipStream_t s);
+// gate: null, or a device flag; the sum then runs only if the flag is nonzero
+hipError_t launch_tree_sum(const double* x, int64_t m, const Work& W, double* out, hipStream_t s,
+                           const int32_t* gate = nullptr);
+hipError_t launch_copy_gated(const int32_t* src, int32_t* dst, int64_t n, const int32_t* gate, hipStream_t s,
+                             int cus);
 hipError_t launch_mcm_init(const Csc& A, const Mcm& M, const Work& W, int32_t long_threshold,
                            hipStream_t s, int cus);
 hipError_t launch_greedy_round(const Csc& A, const Mcm& M, const Work& W, int heavy,

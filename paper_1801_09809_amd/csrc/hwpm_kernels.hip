@@ -1006,8 +1006,9 @@ hipError_t launch_mrk_update(const Csc& A, const Work& W, int slot, bool increme
 // exactly next_pow2(m) leaves.
 
 __global__ __launch_bounds__(256) void k_tree_block(const double* __restrict__ x, int64_t m,
-                                                    double* __restrict__ out) {
+                                                    double* __restrict__ out, const int32_t* __restrict__ gate) {
     __shared__ double part[4];
+    if (gate && *gate == 0) return;  // a gated sum runs only once the rounds have ended
     const int64_t base = (int64_t)blockIdx.x * kTreeBlock + threadIdx.x * 8;
     double v[8];
 #pragma unroll
@@ -1025,8 +1026,9 @@ __global__ __launch_bounds__(256) void k_tree_block(const double* __restrict__ x
 }
 
 __global__ __launch_bounds__(1024) void k_tree_final(const double* __restrict__ x, int64_t m,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, const int32_t* __restrict__ gate) {
     __shared__ double a[kTreeBlock], b[kTreeBlock];
+    if (gate && *gate == 0) return;
     int64_t size = 1;
     while (size < m) size <<= 1;
     for (int64_t t = threadIdx.x; t < size; t += blockDim.x) a[t] = (t < m) ? x[t] : 0.0;
@@ -1041,20 +1043,39 @@ __global__ __launch_bounds__(1024) void k_tree_final(const double* __restrict__ 
     if (threadIdx.x == 0) out[0] = (m > 0) ? src[0] : 0.0;
 }
 
-hipError_t launch_tree_sum(const double* x, int64_t m, const Work& W, double* out, hipStream_t s) {
+hipError_t launch_tree_sum(const double* x, int64_t m, const Work& W, double* out, hipStream_t s,
+                           const int32_t* gate) {
     const double* cur = x;
     double* bufs[2] = {W.tree_a, W.tree_b};
     int which = 0;
     while (m > kTreeBlock) {
         const int64_t blocks = (m + kTreeBlock - 1) / kTreeBlock;
-        hipLaunchKernelGGL(k_tree_block, dim3((unsigned)blocks), dim3(256), 0, s, cur, m, bufs[which]);
+        hipLaunchKernelGGL(k_tree_block, dim3((unsigned)blocks), dim3(256), 0, s, cur, m, bufs[which], gate);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         cur = bufs[which];
         which ^= 1;
         m = blocks;
     }
-    hipLaunchKernelGGL(k_tree_final, dim3(1), dim3(1024), 0, s, cur, m, out);
+    hipLaunchKernelGGL(k_tree_final, dim3(1), dim3(1024), 0, s, cur, m, out, gate);
+    return hipGetLastError();
+}
+
+// dst[0..n) = src[0..n) once *gate is nonzero (the output copy queued behind
+// a batch of rounds before the host knows whether the batch ended them).
+__global__ __launch_bounds__(256) void k_copy_gated(const int32_t* __restrict__ src, int32_t* __restrict__ dst,
+                                                    int64_t n, const int32_t* __restrict__ gate) {
+    if (*gate == 0) return;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_gated(const int32_t* src, int32_t* dst, int64_t n, const int32_t* gate, hipStream_t s,
+                             int cus) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > (int64_t)cus * 8) blocks = (int64_t)cus * 8;
+    hipLaunchKernelGGL(k_copy_gated, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n, gate);
     return hipGetLastError();
 }
 

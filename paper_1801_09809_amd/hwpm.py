@@ -10,7 +10,6 @@ from __future__ import annotations
 
 import ctypes
 import os
-from dataclasses import dataclass
 
 import torch  # loaded first: libhwpm.so then binds to torch's HIP runtime
 
@@ -412,11 +411,23 @@ def hwpm_server_get_stats(server: int) -> hwpm_server_stats:
 # ---------------------------------------------------------------------------
 # convenience wrappers
 
-@dataclass
 class ImproveResult:
-    perm: torch.Tensor      # int32 on the device
-    total: float
-    stats: dict
+    """perm: int32 on the device; total: the matched weight; stats: a dict of
+    the call's hwpm_stats, converted on first access (the conversion costs
+    more host time than the rest of the binding's work per call)."""
+    __slots__ = ("perm", "total", "_raw", "_stats")
+
+    def __init__(self, perm: torch.Tensor, total: float, raw: hwpm_stats):
+        self.perm = perm
+        self.total = total
+        self._raw = raw
+        self._stats = None
+
+    @property
+    def stats(self) -> dict:
+        if self._stats is None:
+            self._stats = self._raw.as_dict()
+        return self._stats
 
 
 class Solver:
@@ -429,6 +440,7 @@ class Solver:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.handle = hwpm_create(device, self.stream.cuda_stream)
         self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+        self._ws_need = {}  # workspace bytes per (n, nnz)
 
     def close(self):
         if self.handle:
@@ -442,7 +454,9 @@ class Solver:
             pass
 
     def _workspace(self, n: int, nnz: int) -> torch.Tensor:
-        need = hwpm_workspace_bytes(n, nnz)
+        need = self._ws_need.get((n, nnz))
+        if need is None:
+            need = self._ws_need[(n, nnz)] = hwpm_workspace_bytes(n, nnz)
         if self.ws.numel() < need:
             self.ws = torch.empty(max(need, 256), dtype=torch.uint8, device=self.device)
         return self.ws
@@ -491,7 +505,7 @@ class Solver:
                                       self.options(**kw))
         if st != HWPM_OK:
             raise HwpmError(st, "hwpm_match")
-        return ImproveResult(perm_out, total, stats.as_dict())
+        return ImproveResult(perm_out, total, stats)
 
     def _batch(self, mats, mates, perms, match: bool, **kw):
         desc = []
@@ -563,7 +577,7 @@ class Solver:
                                         ws.data_ptr(), ws.numel(), opt)
         if st != HWPM_OK:
             raise HwpmError(st, "hwpm_improve")
-        return ImproveResult(perm_out, total, stats.as_dict())
+        return ImproveResult(perm_out, total, stats)
 
 
 class Server:

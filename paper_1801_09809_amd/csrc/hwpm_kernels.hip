@@ -530,6 +530,20 @@ __global__ __launch_bounds__(256) void k_tp_hist(Csc A, Work W, int rb, int32_t 
     for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[(int64_t)b * nseg + seg] = hist[b];
 }
 
+// Inclusive running maximum over the 64 lanes of a wave (values >= -1)
+// with DPP moves: shifts by 1, 2, 4, 8 lanes inside each row of 16, then the
+// last lane of row 0 into row 1 (and of row 2 into row 3), then the last lane
+// of row 1 into rows 2 and 3.  Lanes without a source keep -1.
+__device__ __forceinline__ int32_t wave_incl_max(int32_t v) {
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return v;
+}
+
 // Pass 1b: sort the tile by bucket in LDS, write the triples in runs.
 template <bool POS>
 __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
@@ -568,12 +582,7 @@ __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32
     for (int u = 0; u < U; ++u) {
         const int64_t k = k0 + threadIdx.x + 256 * u;
         sl[u] = (k < A.nnz) ? W.mrk[k] : -1;
-        co[u] = mark[threadIdx.x + 256 * u];
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {  // running max over the wave's part of row u
-            const int32_t v = __shfl_up(co[u], o, 64);
-            if (lane >= o) co[u] = co[u] > v ? co[u] : v;
-        }
+        co[u] = wave_incl_max(mark[threadIdx.x + 256 * u]);  // the wave's part of row u
         if (lane == 63) wmax[4 * u + wave] = co[u];
     }
     __syncthreads();
@@ -586,6 +595,7 @@ __global__ __launch_bounds__(256) void k_tp_scatter(Csc A, Work W, int rb, int32
             int32_t rp = pre;
             for (int w = 0; w < wave; ++w) rp = rp > wmax[4 * u + w] ? rp : wmax[4 * u + w];
             co[u] = co[u] > rp ? co[u] : rp;
+            co[u] = co[u] > cf ? co[u] : cf;  // no-op: every entry's column is >= cf
 #pragma unroll
             for (int w = 0; w < 4; ++w) pre = pre > wmax[4 * u + w] ? pre : wmax[4 * u + w];
         }

@@ -247,16 +247,22 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
     const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
     if (tile >= ntiles) return;  // tile-uniform
     const int32_t j = roots ? roots[tile] : (int32_t)tile;
+    // the root's values are read with its column bounds: one memory round
+    // trip instead of two (wasted for the roots that return below).  The
+    // empty asm statement takes all six as inputs, so the compiler issues
+    // the six loads before it instead of sinking four of them past the
+    // branches below (after the bounds' wait).
+    const int32_t mj = W.mc[j];
+    const double wmj = W.wm[j];
+    const int64_t rs = W.rstart[j];
+    const int32_t rlen = W.rlen[j];
     const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+    asm volatile("" ::"v"(mj), "v"(wmj), "v"(rs), "v"(rlen), "v"(lo), "v"(hi));
     const int64_t len = hi - lo;
     if (len > long_threshold) return;  // split kernel handles it
     if (roots && lane == 0) W.dirty[j] = 0;
     Cand b{0.0, INT32_MAX, -1, -1, -1};
     if (len > 1) {  // a single entry is the matched one: no cycle
-        const int32_t mj = W.mc[j];
-        const double wmj = W.wm[j];
-        const int64_t rs = W.rstart[j];
-        const int32_t rlen = W.rlen[j];
         // a root too long for the tile goes to the wave-per-root kernel
         const bool handoff = len > T * E || rlen > T * E;
         const int sub = blockIdx.x & (kSpread - 1);
@@ -440,16 +446,18 @@ __global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_
     const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
     if (tile >= ntiles) return;  // tile-uniform
     const int32_t j = roots ? roots[tile] : (int32_t)tile;
+    // the root's values are read with its column bounds (as in k_search_chunk)
+    const int32_t mj = W.mc[j];
+    const double wmj = W.wm[j];
+    const int64_t rs = W.rstart[j];
+    const int32_t rlen = W.rlen[j];
     const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+    asm volatile("" ::"v"(mj), "v"(wmj), "v"(rs), "v"(rlen), "v"(lo), "v"(hi));
     const int64_t len = hi - lo;
     if (len > long_threshold) return;  // split kernel handles it
     if (roots && lane == 0) W.dirty[j] = 0;
     Cand b{0.0, INT32_MAX, -1, -1, -1};
     if (len > 1) {
-        const int32_t mj = W.mc[j];
-        const double wmj = W.wm[j];
-        const int64_t rs = W.rstart[j];
-        const int32_t rlen = W.rlen[j];
         const int64_t cb = lo & ~(int64_t)3, rb = rs & ~(int64_t)3;
         // a segment that does not fit its window goes to the wave-per-root kernel
         const bool handoff = !(hi <= cb + 32 && rs + rlen <= rb + 32 && cb + 32 <= A.nnz);

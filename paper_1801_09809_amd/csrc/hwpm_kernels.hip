@@ -66,16 +66,15 @@ hipError_t launch_check_csc(const Csc& A, const Work& W, hipStream_t s, int cus)
 // Set-up: replicate the mates and matched weights (the initial broadcast of
 // Algorithm 2), validate the matching, list the long columns.
 
-// find_row with the final window's nine reads issued together: each index
+// find_row, given the column's bounds, with the final window's nine reads
+// issued together: each index
 // is clamped to the column's last entry (to entry 0 for an empty column, so
 // the matrix must hold at least one entry) and only the slots inside the
 // column can hit.  One thread per column here, so the nine registers are
 // cheap; the search kernels keep find_row.
-__device__ __forceinline__ int64_t find_row_window(const int64_t* __restrict__ col_ptr,
-                                                   const int32_t* __restrict__ row_idx, int32_t c,
-                                                   int32_t r) {
-    int64_t lo = col_ptr[c];
-    const int64_t end = col_ptr[c + 1];
+__device__ __forceinline__ int64_t find_row_window(const int32_t* __restrict__ row_idx, int64_t lo,
+                                                   int64_t end, int32_t r) {
+    // the column is row_idx[lo, end)
     int64_t len = end - lo;
     while (len > 8) {
         const int64_t half = len >> 1;
@@ -106,11 +105,14 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
         const int32_t j = (int32_t)jj;
         W.dgain[j] = 0ull;
         W.droot[j] = kNoRoot;
+        // the mate is read with the column bounds (the empty asm statement
+        // keeps the compiler from sinking its load past the branches below)
         const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+        const int32_t r = mate_in[j];
+        asm volatile("" ::"v"(lo), "v"(hi), "v"(r));
         const bool is_long = hi - lo > long_threshold;
         const int32_t q = wave_append(&W.counters[kNumLong], is_long);
         if (is_long) W.long_list[q] = j;
-        const int32_t r = mate_in[j];
         if (r < 0 || r >= A.n) {
             atomicOr(&W.counters[kErrMatch], 1);
             W.mc[j] = -1;
@@ -118,7 +120,7 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
         }
         W.mr[r] = j;  // a row claimed twice keeps one writer: k_check_match sees the other
         W.mc[j] = r;
-        const int64_t p = find_row_window(A.col_ptr, A.row_idx, j, r);
+        const int64_t p = find_row_window(A.row_idx, lo, hi, r);
         if (p < 0) {
             atomicOr(&W.counters[kErrMatch], 4);
             W.wm[j] = 0.0;
@@ -1071,11 +1073,13 @@ hipError_t launch_tree_sum(const double* x, int64_t m, const Work& W, double* ou
     return hipGetLastError();
 }
 
-// dst[0..n) = src[0..n) once *gate is nonzero (the output copy queued behind
-// a batch of rounds before the host knows whether the batch ended them).
+// dst[0..n) = src[0..n) once *gate is 1 (the output copy queued behind a
+// batch of rounds before the host knows whether the batch ended them; the
+// done flag is 1 when the rounds ended normally, 2 on a failed consistency
+// check, after which the caller's output must stay untouched).
 __global__ __launch_bounds__(256) void k_copy_gated(const int32_t* __restrict__ src, int32_t* __restrict__ dst,
                                                     int64_t n, const int32_t* __restrict__ gate) {
-    if (*gate == 0) return;
+    if (*gate != 1) return;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
 }

@@ -206,7 +206,9 @@ int hwpm_check_csc(hwpm_handle h, const hwpm_csc* A, void* workspace, size_t wor
  *   workspace  device, >= hwpm_workspace_bytes(n, nnz) bytes; its contents
  *              are scratch between calls.
  * Errors: HWPM_EINVAL, HWPM_ENOMEM, HWPM_ETOOBIG, HWPM_EBADCSC (when
- * opt->check_csc), HWPM_EBADMATCH, HWPM_EDEVICE, HWPM_EINTERNAL.
+ * opt->check_csc), HWPM_EBADMATCH (a mate out of range, a row claimed twice,
+ * a mate row that is not an entry of its column, or nnz < n; checked before
+ * the first round, perm_out untouched), HWPM_EDEVICE, HWPM_EINTERNAL.
  * n = 0 returns HWPM_OK with total 0.0. */
 int hwpm_improve(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
                  double* total_out, const hwpm_options* opt, hwpm_stats* stats,

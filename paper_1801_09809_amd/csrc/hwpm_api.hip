@@ -98,6 +98,9 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     const bool timing = opt.timing == 1;   // every stage
     const bool tsearch = opt.timing != 0;  // the search stage (both levels)
     hipEvent_t* ev = h->ev;
+    // a perfect matching takes n distinct entries: with fewer, none lies in
+    // the pattern (and the set-up's search assumes at least one entry)
+    if (A.nnz < (int64_t)n) return HWPM_EBADMATCH;
     int probe = opt.probe ? opt.probe : kDefaultProbe;
     // default tile: 4 lanes per root for short columns, 8 from about 20
     // entries per column on (the chunked kernel then holds 32 per tile either way)

@@ -256,25 +256,66 @@ def test_bad_csc_rejected(solver):
     assert solver.check_csc(_dev(wl.col_ptr, dev), _dev(ri, dev), _dev(wl.w, dev)) == E
 
 
-def test_bad_matching_rejected(solver):
+@pytest.mark.parametrize("probe", [1, 2, 3, 4, 5])
+def test_bad_matching_rejected(solver, probe):
     from paper_1801_09809_amd import hwpm
     wl = small_random(100, 4, 3)
     E = hwpm.HWPM_EBADMATCH
     m = wl.planted.copy(); m[3] = m[4]            # duplicate row
-    _expect(solver, E, wl.col_ptr, wl.row_idx, wl.w, m)
+    _expect(solver, E, wl.col_ptr, wl.row_idx, wl.w, m, probe=probe)
     m = wl.planted.copy(); m[3] = wl.n            # out of range
-    _expect(solver, E, wl.col_ptr, wl.row_idx, wl.w, m)
+    _expect(solver, E, wl.col_ptr, wl.row_idx, wl.w, m, probe=probe)
     m = wl.planted.copy(); m[0] = -1
-    _expect(solver, E, wl.col_ptr, wl.row_idx, wl.w, m)
+    _expect(solver, E, wl.col_ptr, wl.row_idx, wl.w, m, probe=probe)
     # a permutation that uses a structural zero
     a = ck.dense_from_workload(wl)
     for j in range(wl.n):
         for c in range(wl.n):
             if c != j and np.isnan(a[wl.planted[c], j]):
                 m = wl.planted.copy(); m[j], m[c] = m[c], m[j]
-                _expect(solver, E, wl.col_ptr, wl.row_idx, wl.w, m)
+                _expect(solver, E, wl.col_ptr, wl.row_idx, wl.w, m, probe=probe)
                 return
     pytest.fail("no structural zero found")
+
+
+@pytest.mark.parametrize("probe", [1, 3, 5])
+def test_structural_zero_matching_leaves_outputs(solver, probe):
+    """A permutation with one mate row outside its column, on a matrix of many
+    transpose tiles: HWPM_EBADMATCH before any round, the output untouched,
+    and a valid solve on the same handle right after gives the oracle's
+    result."""
+    from paper_1801_09809_amd import hwpm
+    dev = solver.device
+    wl = small_random(20000, 8, 17)
+    col0 = set(wl.row_idx[wl.col_ptr[0]:wl.col_ptr[1]].tolist())
+    c = next(c for c in range(1, wl.n) if int(wl.planted[c]) not in col0)
+    m = wl.planted.copy(); m[0], m[c] = m[c], m[0]
+    cp, ri, w = _dev(wl.col_ptr, dev), _dev(wl.row_idx, dev), _dev(wl.w, dev)
+    perm = torch.full((wl.n,), -7, dtype=torch.int32, device=dev)
+    print(f"[gpu] structural zero n={wl.n} probe={probe} column 0 <-> {c}", flush=True)
+    with pytest.raises(hwpm.HwpmError) as e:
+        solver.improve(cp, ri, w, _dev(m, dev), perm_out=perm, probe=probe)
+    assert e.value.status == hwpm.HWPM_EBADMATCH
+    assert bool((perm == -7).all())
+    res = solver.improve(cp, ri, w, _dev(wl.planted, dev), perm_out=perm, probe=probe)
+    ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
+    assert np.array_equal(perm.cpu().numpy(), ref.perm)
+    assert np.float64(res.total).tobytes() == np.float64(ref.total).tobytes()
+    assert np.float64(res.stats["init_weight"]).tobytes() == np.float64(ref.init_weight).tobytes()
+
+
+@pytest.mark.parametrize("probe", [1, 2, 3, 4, 5])
+def test_matching_without_entries(solver, probe):
+    """n > 0 columns and no entries: no perfect matching lies in the
+    pattern, whatever permutation is given (refused on the host, before any
+    kernel reads the empty entry arrays)."""
+    from paper_1801_09809_amd import hwpm
+    n = 7
+    col_ptr = np.zeros(n + 1, dtype=np.int64)
+    ri, w = np.zeros(0, dtype=np.int32), np.zeros(0, dtype=np.float64)
+    mate = np.arange(n, dtype=np.int32)
+    _expect(solver, hwpm.HWPM_EBADMATCH, col_ptr, ri, w, mate, probe=probe)
+    _expect(solver, hwpm.HWPM_EBADMATCH, col_ptr, ri, w, mate, probe=probe, check_csc=False)
 
 
 # ---------------------------------------------------------------------------

@@ -698,6 +698,8 @@ int hwpm_match(hwpm_handle h, const hwpm_csc* Ain, int32_t* perm_out, double* to
         st = timed_check(h, A, W, timing, &S);
         if (st != HWPM_OK) return st;
     }
+    // a perfect matching takes n distinct entries
+    if (A.nnz < (int64_t)n) return HWPM_ESINGULAR;
     st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, timing, &S);
     if (st != HWPM_OK) return st;
     double total = 0.0;

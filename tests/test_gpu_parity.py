@@ -464,6 +464,26 @@ def test_match_singular(solver):
             assert np.array_equal(perm.cpu().numpy(), ref.perm) and res.total == ref.total
 
 
+def test_match_fewer_entries_than_columns(solver):
+    """No perfect matching fits in fewer than n entries: HWPM_ESINGULAR (as
+    the oracle finds), refused on the host, the output untouched."""
+    from paper_1801_09809_amd import hwpm
+    from oracle import oracle_match
+    dev = solver.device
+    cases = [(np.zeros(7, dtype=np.int64), np.zeros(0, dtype=np.int32)),       # n = 6, no entries
+             (np.array([0, 1, 2, 3, 3], dtype=np.int64), np.array([2, 0, 1], dtype=np.int32))]  # n = 4, 3 entries
+    for cp, ri in cases:
+        n = cp.size - 1
+        w = np.linspace(1.0, 2.0, ri.size)
+        assert oracle_match(n, cp, ri, w).status == -2
+        for check in (True, False):
+            perm = torch.full((n,), -7, dtype=torch.int32, device=dev)
+            with pytest.raises(hwpm.HwpmError) as e:
+                solver.match(_dev(cp, dev), _dev(ri, dev), _dev(w, dev), perm_out=perm, check_csc=check)
+            assert e.value.status == hwpm.HWPM_ESINGULAR
+            assert (perm.cpu().numpy() == -7).all()
+
+
 @pytest.mark.parametrize("k", [1, 2])
 def test_match_full_workload(solver, k):
     wl = workload(k)

@@ -589,6 +589,40 @@ def test_match_batch_equals_alone_with_singular(solver, plain):
         assert it["rounds"] == ref.rounds
 
 
+def test_batch_members_without_entries(solver):
+    """A member with columns but no entries: hwpm_match_batch reports it
+    singular (as the oracle does) and solves the others; hwpm_improve_batch
+    rejects the batch's matching; a batch of such members only is all
+    singular."""
+    from paper_1801_09809_amd import hwpm
+    from oracle import oracle_match
+    dev = solver.device
+    empty5 = (np.zeros(6, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0, dtype=np.float64))
+    empty3 = (np.zeros(4, dtype=np.int64), np.zeros(0, dtype=np.int32), np.zeros(0, dtype=np.float64))
+    good = [small_random(300, 3, 1), small_random(200, 3, 2)]
+    host = [(good[0].col_ptr, good[0].row_idx, good[0].w), empty5, (good[1].col_ptr, good[1].row_idx, good[1].w)]
+    mats = [tuple(_dev(a, dev) for a in m) for m in host]
+    perms = [torch.full((m[0].size - 1,), -7, dtype=torch.int32, device=dev) for m in host]
+    print("[gpu] batch with an entry-less member", flush=True)
+    perms, totals, items, _ = solver.match_batch(mats, perms=perms)
+    for (cp, ri, w), p, t, it in zip(host, perms, totals, items):
+        ref = oracle_match(cp.size - 1, cp, ri, w)
+        if ref.status == -2:
+            assert it["status"] == -2 and (p.cpu().numpy() == -7).all()
+            continue
+        assert it["status"] == 0 and np.array_equal(p.cpu().numpy(), ref.perm)
+        assert np.float64(t).tobytes() == np.float64(ref.total).tobytes()
+    assert [it["status"] for it in items] == [0, -2, 0]
+    mates = [_dev(good[0].planted, dev), _dev(np.arange(5, dtype=np.int32), dev), _dev(good[1].planted, dev)]
+    with pytest.raises(hwpm.HwpmError) as e:
+        solver.improve_batch(mats, mates)
+    assert e.value.status == hwpm.HWPM_EBADMATCH
+    print("[gpu] batch of entry-less members only", flush=True)
+    mats = [tuple(_dev(a, dev) for a in m) for m in (empty5, empty3)]
+    perms, totals, items, _ = solver.match_batch(mats)
+    assert [it["status"] for it in items] == [-2, -2]
+
+
 def test_batch_rejects_bad_member(solver):
     from paper_1801_09809_amd import hwpm
     dev = solver.device

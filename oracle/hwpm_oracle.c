@@ -36,8 +36,11 @@
  * brute-force enumeration, hand-derived cases, closed forms and the 6-cycle
  * counterexample of Section 4.  Phase I (greedy + MCM) is pinned for
  * cardinality (a maximum matching, checked against a library
- * Hopcroft-Karp) and maximality; its tie-break order is a reading of
- * Section 5.2 and is otherwise parity unpinned.
+ * Hopcroft-Karp) and maximality, and each of its rules (heavy-edge
+ * preference, equal-weight ties by index, the heavier BFS parent, the
+ * smallest endpoint per tree, a tree stopping at its first endpoint) by a
+ * hand-derived case whose misreadings give a different matching or a
+ * different phase and level count.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -53,6 +56,11 @@ typedef struct {
     double final_weight;
     int32_t round_candidates[ORACLE_MAX_ROUND_STATS]; /* |S| per round */
     int32_t round_applied[ORACLE_MAX_ROUND_STATS];    /* |D(S)| per round */
+    /* Phase I counts (oracle_match only; 0 otherwise) */
+    int32_t greedy_rounds;      /* proposal rounds, the last one finding no proposal */
+    int32_t greedy_cardinality; /* size of the greedy maximal matching */
+    int32_t mcm_phases;         /* BFS phases started with an unmatched column */
+    int32_t mcm_levels;         /* BFS levels with a nonempty frontier, all phases */
 } oracle_stats;
 
 /* ------------------------------------------------------------------------ */
@@ -241,11 +249,15 @@ int oracle_improve(int32_t n, const int64_t* col_ptr, const int32_t* row_idx, co
  * The rounds stop when no unmatched column has an unmatched neighbour, so
  * the result is maximal.  With heavy == 0 the weights are ignored (the
  * ablation "without heuristic", Section 6.2): only the index order decides.
- * mc[j] / mr[i] receive the mates or -1.  Returns the cardinality. */
+ * mc[j] / mr[i] receive the mates or -1; *rounds_out (nullable) the number
+ * of proposal rounds run, counting the last one, which finds no proposal.
+ * Returns the cardinality. */
 int32_t oracle_greedy(int32_t n, const int64_t* col_ptr, const int32_t* row_idx,
-                      const double* w, int32_t heavy, int32_t* mc, int32_t* mr)
+                      const double* w, int32_t heavy, int32_t* mc, int32_t* mr,
+                      int32_t* rounds_out)
 {
     for (int32_t v = 0; v < n; ++v) { mc[v] = -1; mr[v] = -1; }
+    if (rounds_out) *rounds_out = 0;
     if (n <= 0) return 0;
     size_t N = (size_t)n;
     int32_t* prop_row = (int32_t*)malloc(N * sizeof(int32_t)); /* row column j proposes to */
@@ -254,6 +266,7 @@ int32_t oracle_greedy(int32_t n, const int64_t* col_ptr, const int32_t* row_idx,
     int32_t card = 0;
     for (;;) {
         int32_t any = 0;
+        if (rounds_out) ++*rounds_out;
         for (int32_t j = 0; j < n; ++j) {
             prop_row[j] = -1;
             if (mc[j] >= 0) continue;
@@ -308,10 +321,16 @@ int32_t oracle_greedy(int32_t n, const int64_t* col_ptr, const int32_t* row_idx,
  *     are vertex-disjoint, so the paths are too).
  * Phases repeat until one finds no path.  mc/mr hold a matching on entry
  * (e.g. from oracle_greedy) and the maximum matching on return.
- * Returns the cardinality. */
+ * *phases_out (nullable) receives the number of phases started with an
+ * unmatched column (the last of them finds no path unless the matching
+ * became perfect), *levels_out (nullable) the number of levels with a
+ * nonempty frontier over all phases.  Returns the cardinality. */
 int32_t oracle_mcm(int32_t n, const int64_t* col_ptr, const int32_t* row_idx, const double* w,
-                   int32_t heavy, int32_t* mc, int32_t* mr)
+                   int32_t heavy, int32_t* mc, int32_t* mr, int32_t* phases_out,
+                   int32_t* levels_out)
 {
+    if (phases_out) *phases_out = 0;
+    if (levels_out) *levels_out = 0;
     if (n <= 0) return 0;
     size_t N = (size_t)n;
     int32_t* parent = (int32_t*)malloc(N * sizeof(int32_t));   /* row -> column it was reached from */
@@ -330,8 +349,10 @@ int32_t oracle_mcm(int32_t n, const int64_t* col_ptr, const int32_t* row_idx, co
         for (int32_t j = 0; j < n; ++j)
             if (mc[j] < 0) { frontier[nf++] = j; tree_of_col[j] = j; }
         if (nf == 0) break;                       /* already perfect */
+        if (phases_out) ++*phases_out;
         int32_t found_any = 0;
         while (nf > 0) {
+            if (levels_out) ++*levels_out;
             /* visit rows adjacent to the frontier; pick the parent by (w desc, col asc) */
             int32_t nl = 0;
             for (int32_t f = 0; f < nf; ++f) {
@@ -415,12 +436,23 @@ int oracle_match(int32_t n, const int64_t* col_ptr, const int32_t* row_idx, cons
     size_t N = (size_t)n;
     int32_t* mc = (int32_t*)malloc(N * sizeof(int32_t));
     int32_t* mr = (int32_t*)malloc(N * sizeof(int32_t));
-    oracle_greedy(n, col_ptr, row_idx, w, heavy, mc, mr);
-    int32_t card = oracle_mcm(n, col_ptr, row_idx, w, heavy, mc, mr);
+    int32_t g_rounds = 0, phases = 0, levels = 0;
+    const int32_t g_card = oracle_greedy(n, col_ptr, row_idx, w, heavy, mc, mr, &g_rounds);
+    int32_t card = oracle_mcm(n, col_ptr, row_idx, w, heavy, mc, mr, &phases, &levels);
     if (mcm_card_out) *mcm_card_out = card;
     int rc = 0;
-    if (card < n) rc = -2;
-    else rc = oracle_improve(n, col_ptr, row_idx, w, mc, max_rounds, perm_out, total_out, st);
+    if (card < n) {
+        rc = -2;
+        if (st) memset(st, 0, sizeof(*st));
+    } else {
+        rc = oracle_improve(n, col_ptr, row_idx, w, mc, max_rounds, perm_out, total_out, st);
+    }
+    if (st) {
+        st->greedy_rounds = g_rounds;
+        st->greedy_cardinality = g_card;
+        st->mcm_phases = phases;
+        st->mcm_levels = levels;
+    }
     free(mc); free(mr);
     return rc;
 }

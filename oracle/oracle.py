@@ -28,6 +28,10 @@ class _Stats(ctypes.Structure):
         ("final_weight", ctypes.c_double),
         ("round_candidates", ctypes.c_int32 * MAX_ROUND_STATS),
         ("round_applied", ctypes.c_int32 * MAX_ROUND_STATS),
+        ("greedy_rounds", ctypes.c_int32),
+        ("greedy_cardinality", ctypes.c_int32),
+        ("mcm_phases", ctypes.c_int32),
+        ("mcm_levels", ctypes.c_int32),
     ]
 
 
@@ -58,9 +62,9 @@ def _load():
         lib.oracle_improve.argtypes = [ctypes.c_int32, p, p, p, p, ctypes.c_int32, p, p,
                                        ctypes.POINTER(_Stats)]
         lib.oracle_greedy.restype = ctypes.c_int32
-        lib.oracle_greedy.argtypes = [ctypes.c_int32, p, p, p, ctypes.c_int32, p, p]
+        lib.oracle_greedy.argtypes = [ctypes.c_int32, p, p, p, ctypes.c_int32, p, p, p]
         lib.oracle_mcm.restype = ctypes.c_int32
-        lib.oracle_mcm.argtypes = [ctypes.c_int32, p, p, p, ctypes.c_int32, p, p]
+        lib.oracle_mcm.argtypes = [ctypes.c_int32, p, p, p, ctypes.c_int32, p, p, p, p]
         lib.oracle_match.restype = ctypes.c_int
         lib.oracle_match.argtypes = [ctypes.c_int32, p, p, p, ctypes.c_int32, ctypes.c_int32,
                                      p, p, ctypes.POINTER(_Stats), p]
@@ -92,6 +96,10 @@ class OracleResult:
     round_candidates: list = field(default_factory=list)
     round_applied: list = field(default_factory=list)
     mcm_cardinality: int = -1
+    greedy_rounds: int = 0
+    greedy_cardinality: int = 0
+    mcm_phases: int = 0
+    mcm_levels: int = 0
 
 
 def _result(status, perm, total, st: _Stats, card=-1) -> OracleResult:
@@ -101,7 +109,9 @@ def _result(status, perm, total, st: _Stats, card=-1) -> OracleResult:
         hit_round_cap=bool(st.hit_round_cap), cycles_applied=st.cycles_applied,
         init_weight=st.init_weight, final_weight=st.final_weight,
         round_candidates=list(st.round_candidates[:nr]),
-        round_applied=list(st.round_applied[:nr]), mcm_cardinality=card)
+        round_applied=list(st.round_applied[:nr]), mcm_cardinality=card,
+        greedy_rounds=st.greedy_rounds, greedy_cardinality=st.greedy_cardinality,
+        mcm_phases=st.mcm_phases, mcm_levels=st.mcm_levels)
 
 
 def oracle_tree_sum(x) -> float:
@@ -121,20 +131,31 @@ def oracle_improve(n, col_ptr, row_idx, w, mate_in, max_rounds: int = 0) -> Orac
     return _result(rc, perm, total.value, st)
 
 
-def oracle_greedy(n, col_ptr, row_idx, w, heavy: bool = True):
+def _i32_out():
+    v = ctypes.c_int32(0)
+    return v, ctypes.cast(ctypes.pointer(v), ctypes.c_void_p)
+
+
+def oracle_greedy(n, col_ptr, row_idx, w, heavy: bool = True, counts: bool = False):
+    """(cardinality, mc, mr); with counts=True also the number of proposal rounds."""
     col_ptr, row_idx, w = _csc(col_ptr, row_idx, w)
     mc = np.empty(max(n, 0), dtype=np.int32)
     mr = np.empty(max(n, 0), dtype=np.int32)
-    card = _load().oracle_greedy(n, _ptr(col_ptr), _ptr(row_idx), _ptr(w), int(heavy), _ptr(mc), _ptr(mr))
-    return card, mc, mr
+    rounds, rp = _i32_out()
+    card = _load().oracle_greedy(n, _ptr(col_ptr), _ptr(row_idx), _ptr(w), int(heavy), _ptr(mc), _ptr(mr), rp)
+    return (card, mc, mr, rounds.value) if counts else (card, mc, mr)
 
 
-def oracle_mcm(n, col_ptr, row_idx, w, mc, mr, heavy: bool = True):
+def oracle_mcm(n, col_ptr, row_idx, w, mc, mr, heavy: bool = True, counts: bool = False):
+    """(cardinality, mc, mr) from the matching (mc, mr); with counts=True also
+    the number of BFS phases and of levels."""
     col_ptr, row_idx, w = _csc(col_ptr, row_idx, w)
     mc = np.array(mc, dtype=np.int32, copy=True)
     mr = np.array(mr, dtype=np.int32, copy=True)
-    card = _load().oracle_mcm(n, _ptr(col_ptr), _ptr(row_idx), _ptr(w), int(heavy), _ptr(mc), _ptr(mr))
-    return card, mc, mr
+    phases, pp = _i32_out()
+    levels, lp = _i32_out()
+    card = _load().oracle_mcm(n, _ptr(col_ptr), _ptr(row_idx), _ptr(w), int(heavy), _ptr(mc), _ptr(mr), pp, lp)
+    return (card, mc, mr, phases.value, levels.value) if counts else (card, mc, mr)
 
 
 def oracle_match(n, col_ptr, row_idx, w, heavy: bool = True, max_rounds: int = 0) -> OracleResult:

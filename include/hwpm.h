@@ -92,21 +92,25 @@ typedef struct {
      * between two kernels also holds the second one back, so fewer events
      * perturb the solve less).  Other values: HWPM_EINVAL. */
     int32_t timing;
-    /* Lanes per column in the cycle-search kernel: 0 = default (4; 8 with
-     * probe 3 when the matrix has more than 20 entries per column on
-     * average), else one of 4, 8, 16, 32, 64.  Results do not depend on it. */
+    /* Lanes per root column in the cycle-search kernel: 0 = default (4; 8 with
+     * probes 3 and 5 when the matrix has more than 20 entries per column on
+     * average), else one of 4, 8, 16, 32, 64 (64: probes 1 and 2 only).
+     * Results do not depend on it. */
     int32_t tile_width;
     /* How the closing edge {m_j, m_i} is probed (results do not depend on it):
-     * 0 = default; 1 = binary search of row m_j in column m_i; 2 = build the
-     * pattern transpose once per call and test m_i against the row list of
-     * m_j (the marking trick of Section 4), with per-entry mate columns kept
-     * up to date across flips, one entry per lane; 3 = the same with 8
-     * entries per lane in 4-lane tiles; 4 = the same with 16-byte vector
-     * loads (used when row_idx is 16-byte aligned, else 3); 5 = probe 3 over
-     * row lists built without CSC positions (a lighter transpose; a hit or a
-     * mate refresh binary-searches its entry instead: the better choice when
-     * hits are rare).  Probes 2-5 keep 32-bit CSC positions: a matrix with
-     * nnz >= 2^31 uses probe 1. */
+     * 0 = default (3); 1 = binary search of row m_j in column m_i; 2 = build
+     * the pattern transpose once per call and test m_i against the row list
+     * of m_j (the marking trick of Section 4), with per-entry mate columns
+     * kept up to date across flips, one entry per lane; 3 = the same, each
+     * root's row list loaded by a tile of lanes and summarised in a two-word
+     * filter, and only the probes that pass it compared with the list (the
+     * default); 4 = the same with every probe compared against the whole
+     * row list through cross-lane exchanges;
+     * 5 = probe 3 over row lists built without CSC positions (a lighter
+     * transpose; a hit or a mate refresh binary-searches its entry instead:
+     * the better choice when hits are rare).  Probes 2-5 read only the
+     * entries of column j after its matched one (the rows i > m_j) and keep
+     * 32-bit CSC positions: a matrix with nnz >= 2^31 uses probe 1. */
     int32_t probe;
     /* Initial matching of hwpm_match (Section 5.2): 0 = heavy-edge tie-break
      * in the greedy and BFS steps (the paper's heuristic, default);
@@ -129,7 +133,7 @@ typedef struct {
     int32_t greedy_rounds;   /* hwpm_match: proposal rounds of the greedy step */
     int32_t greedy_cardinality; /* hwpm_match: size of the greedy maximal matching */
     int32_t mcm_cardinality; /* hwpm_match: size of the maximum matching */
-    int32_t mcm_phases;      /* hwpm_match: BFS phases that augmented */
+    int32_t mcm_phases;      /* hwpm_match: BFS phases run (each starts with an unmatched column) */
     int32_t mcm_levels;      /* hwpm_match: BFS levels over all phases */
     double init_weight;      /* total weight of the starting perfect matching */
     double final_weight;     /* = *total_out */

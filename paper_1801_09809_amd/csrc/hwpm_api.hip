@@ -106,8 +106,6 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     // entries per column on (the chunked kernel then holds 32 per tile either way)
     const int tile = opt.tile_width ? opt.tile_width
                                     : ((probe == 3 || probe == 5) && A.nnz > 20 * (int64_t)A.n ? 8 : kDefaultTile);
-    // the vector kernel reads row_idx in aligned 16-byte windows
-    if (probe == 4 && ((uintptr_t)A.row_idx & 15)) probe = 3;
     // the row lists keep 32-bit CSC positions
     if (probe >= 2 && A.nnz >= ((int64_t)1 << 31)) probe = 1;
     // probe 5: the chunked kernels over row lists built without CSC positions
@@ -287,7 +285,7 @@ int check_options(const hwpm_options& opt) {
     if (tile != 4 && tile != 8 && tile != 16 && tile != 32 && tile != 64) return HWPM_EINVAL;
     const int probe = opt.probe ? opt.probe : kDefaultProbe;
     if (probe < 1 || probe > 5) return HWPM_EINVAL;
-    if ((probe == 3 || probe == 5) && tile == 64) return HWPM_EINVAL;
+    if (probe >= 3 && tile == 64) return HWPM_EINVAL;
     if (opt.mcm_plain != 0 && opt.mcm_plain != 1) return HWPM_EINVAL;
     if (opt.full_search != 0 && opt.full_search != 1) return HWPM_EINVAL;
     if (opt.timing < 0 || opt.timing > 2) return HWPM_EINVAL;

@@ -1,9 +1,12 @@
 // Device helpers shared by the search and round kernels: the closing-edge
 // probe by binary search, the Step-C winner record and its order, the
-// cross-lane winner reduction and the column hash of the LDS tables.
+// cross-lane winner reduction and the LDS hash sets (hwpm_hash.h).
 #pragma once
 
 #include "hwpm_internal.h"
+
+#define HWPM_HD __device__ __forceinline__
+#include "hwpm_hash.h"
 
 namespace hwpm {
 
@@ -92,31 +95,44 @@ __device__ __forceinline__ void find_row_x4(const int64_t* __restrict__ col_ptr,
     }
 }
 
-// Winner order of Step C: larger gain first, then smaller row.
+// Winner order of Step C: larger gain first, then smaller row i.  Every
+// candidate of one root lies in the root's own column j, whose rows increase
+// with the CSC position, so the smaller row is the smaller position k: the
+// search keys candidates by k and reads the row of the winner only.
 struct Cand {
     double g;     // 0.0 = none (candidates have g > 0)
-    int32_t i;    // INT32_MAX = none
-    int32_t c;
-    int64_t k;
-    int64_t p;
+    int64_t k;    // position of {i, j}; INT64_MAX = none
+    int32_t c;    // other column c = m_i
+    int64_t p;    // position of {m_j, m_i}
 };
 
-__device__ __forceinline__ bool better(double g1, int32_t i1, double g2, int32_t i2) {
-    return g1 > g2 || (g1 == g2 && i1 < i2);
+constexpr int64_t kNoPos = INT64_MAX;
+
+__device__ __forceinline__ bool better(double g1, int64_t k1, double g2, int64_t k2) {
+    return g1 > g2 || (g1 == g2 && k1 < k2);
 }
 
 // Record the Step-C winner of root j (or its absence).
-__device__ __forceinline__ void publish(const Work& W, int32_t j, const Cand& b, int slot) {
-    (void)slot;
-    if (b.i == INT32_MAX) {
+__device__ __forceinline__ void publish(const Csc& A, const Work& W, int32_t j, const Cand& b) {
+    if (b.k == kNoPos) {
         W.best_i[j] = -1;
         return;
     }
-    W.best_i[j] = b.i;
+    W.best_i[j] = A.row_idx[b.k];
     W.best_g[j] = b.g;
     W.best_c[j] = b.c;
     W.best_k[j] = b.k;
     W.best_p[j] = b.p;
+}
+
+// Fold a candidate into the running winner.
+__device__ __forceinline__ void offer(Cand& b, double g, int64_t k, int32_t c, int64_t p) {
+    if (g > 0.0 && better(g, k, b.g, b.k)) {
+        b.g = g;
+        b.k = k;
+        b.c = c;
+        b.p = p;
+    }
 }
 
 // One entry {i, j} of root column j (mate row mj, matched weight wmj):
@@ -128,14 +144,7 @@ __device__ __forceinline__ void try_entry(const Csc& A, const Work& W, int64_t k
     const int32_t mi = W.mr[i];
     const int64_t p = find_row(A.col_ptr, A.row_idx, mi, mj);  // edge {m_j, m_i}
     if (p < 0) return;
-    const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
-    if (g > 0.0 && better(g, i, b.g, b.i)) {
-        b.g = g;
-        b.i = i;
-        b.c = mi;
-        b.k = k;
-        b.p = p;
-    }
+    offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + wmj), k, mi, p);
 }
 
 template <int WIDTH>
@@ -143,34 +152,29 @@ __device__ __forceinline__ void reduce_best(Cand& b) {
 #pragma unroll
     for (int off = WIDTH / 2; off >= 1; off >>= 1) {
         const double og = __shfl_xor(b.g, off, WIDTH);
-        const int32_t oi = __shfl_xor(b.i, off, WIDTH);
-        const int32_t oc = __shfl_xor(b.c, off, WIDTH);
         const int64_t ok = __shfl_xor(b.k, off, WIDTH);
+        const int32_t oc = __shfl_xor(b.c, off, WIDTH);
         const int64_t op = __shfl_xor(b.p, off, WIDTH);
-        if (better(og, oi, b.g, b.i)) {
+        if (better(og, ok, b.g, b.k)) {
             b.g = og;
-            b.i = oi;
-            b.c = oc;
             b.k = ok;
+            b.c = oc;
             b.p = op;
         }
     }
 }
 
-// Hash of a column index into a power-of-two table (Fibonacci hashing).
-__device__ __forceinline__ uint32_t hash_col(int32_t c, uint32_t mask) {
-    return ((uint32_t)c * 0x9E3779B1u >> 12) & mask;
-}
-
-// Lookup in an LDS open-addressing table (keys hk, values hv, empty key -1,
-// size mask + 1, linear probing): the value stored with key c, else -1.
-__device__ __forceinline__ int32_t hash_find(const int32_t* hk, const int32_t* hv, int32_t c, uint32_t mask) {
-    for (uint32_t h = hash_col(c, mask);; h = (h + 1) & mask) {
-        const int32_t key = hk[h];
-        if (key == c) return hv[h];
-        if (key == -1) return -1;
+// Compare-and-swap on an LDS slot, for the hash sets of hwpm_hash.h.
+struct LdsCas32 {
+    __device__ __forceinline__ int32_t operator()(int32_t* p, int32_t expected, int32_t desired) const {
+        return atomicCAS(p, expected, desired);
     }
-}
+};
 
+// LDS writes of the wave are done and visible to its lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 }  // namespace hwpm

@@ -90,8 +90,7 @@ struct Work {
     int32_t* long_list; // columns searched by the split kernel
     int64_t* chunk_off; // chunk prefix per long column (n_long + 1)
     int32_t* chunk_col; // long column (index into long_list) of every chunk
-    double* part_g;     // per-chunk partial winners
-    int32_t* part_i;
+    double* part_g;     // per-chunk partial winners (position keyed)
     int32_t* part_c;
     int64_t* part_k;
     int64_t* part_p;
@@ -105,8 +104,10 @@ struct Work {
     // transposed probe
     int64_t* rowptr;    // n + 1: row lists laid out by the column matched to
                         // each row when the call starts (slot order)
-    int64_t* rstart;    // n: start of the row list of the row matched to column j
-    int32_t* rlen;      // n: its length
+    int2* rsl;          // n: (start, length) of the row list of the row matched to column j
+    int32_t* cp32;      // n + 1: 32-bit copy of col_ptr (transposed probes, nnz < 2^31)
+    int32_t* pm;        // n: CSC position of column j's matched entry {m_j, j} (transposed
+                        // probes): the rows i > m_j of column j are the positions after it
     int32_t* colidx;    // nnz: columns of each row (any order within a row)
     int32_t* cscpos;    // nnz: CSC position of each row-list entry (transposed probes need nnz < 2^31);
                         // null when the lists are built without positions (probe 5)

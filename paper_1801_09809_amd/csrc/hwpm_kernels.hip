@@ -98,8 +98,10 @@ __device__ __forceinline__ int64_t find_row_window(const int32_t* __restrict__ r
     return hit;
 }
 
+// With pos32 (nnz < 2^31) it also fills the 32-bit column pointers and the
+// matched positions the transposed searches read.
 __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
-                             int32_t long_threshold) {
+                             int32_t long_threshold, int pos32) {
     for (int64_t jj = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; jj < A.n;
          jj += (int64_t)gridDim.x * blockDim.x) {
         const int32_t j = (int32_t)jj;
@@ -113,6 +115,10 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
         const bool is_long = hi - lo > long_threshold;
         const int32_t q = wave_append(&W.counters[kNumLong], is_long);
         if (is_long) W.long_list[q] = j;
+        if (pos32) {
+            W.cp32[j] = (int32_t)lo;
+            if (j == A.n - 1) W.cp32[A.n] = (int32_t)hi;
+        }
         if (r < 0 || r >= A.n) {
             atomicOr(&W.counters[kErrMatch], 1);
             W.mc[j] = -1;
@@ -127,6 +133,7 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
         } else {
             W.wm[j] = A.w[p];
         }
+        if (pos32) W.pm[j] = (int32_t)p;
     }
 }
 
@@ -144,7 +151,8 @@ hipError_t launch_init_match(const Csc& A, const Work& W, const int32_t* mate_in
                              int32_t long_threshold, hipStream_t s) {
     const int64_t blocks = ((int64_t)A.n + 255) / 256;
     const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
-    hipLaunchKernelGGL(k_init_match, dim3(g), dim3(256), 0, s, A, W, mate_in, long_threshold);
+    const int pos32 = A.nnz < ((int64_t)1 << 31) ? 1 : 0;
+    hipLaunchKernelGGL(k_init_match, dim3(g), dim3(256), 0, s, A, W, mate_in, long_threshold, pos32);
     hipLaunchKernelGGL(k_check_match, dim3(g), dim3(256), 0, s, A, W);
     return hipGetLastError();
 }
@@ -274,11 +282,13 @@ __global__ void k_apply(Csc A, Work W, int slot, int transposed) {
         W.dgain[c] = 0ull;
         __hip_atomic_store(&W.droot[c], kNoRoot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (transposed) {
-            // the row lists follow their rows: j now holds row i (was c's)
-            const int64_t sj = W.rstart[j], sc = W.rstart[c];
-            const int32_t lj = W.rlen[j], lc = W.rlen[c];
-            W.rstart[j] = sc; W.rlen[j] = lc;
-            W.rstart[c] = sj; W.rlen[c] = lj;
+            // the row lists follow their rows: j now holds row i (was c's),
+            // and the matched positions follow the flip
+            const int2 sj = W.rsl[j], sc = W.rsl[c];
+            W.rsl[j] = sc;
+            W.rsl[c] = sj;
+            W.pm[j] = (int32_t)W.best_k[j];
+            W.pm[c] = (int32_t)W.best_p[j];
         }
         if (W.mat_of_col) {
             const int32_t blk = W.mat_of_col[j];
@@ -410,13 +420,12 @@ __global__ __launch_bounds__(256) void k_row_fill_long(Csc A, Work W) {
     }
 }
 
-// Slot pointers of the row lists: rstart/rlen of column j locate the list of
+// Slot pointers of the row lists: rsl[j] = (start, length) of the list of
 // the row matched to j.
 __global__ void k_slot_ptrs(Csc A, Work W) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < A.n;
          j += (int64_t)gridDim.x * blockDim.x) {
-        W.rstart[j] = W.rowptr[j];
-        W.rlen[j] = (int32_t)(W.rowptr[j + 1] - W.rowptr[j]);
+        W.rsl[j] = make_int2((int32_t)W.rowptr[j], (int32_t)(W.rowptr[j + 1] - W.rowptr[j]));
     }
 }
 
@@ -806,13 +815,11 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
         rc[2 * t + 1] = ex + a0;
         if (2 * t < nr) {
             W.rowptr[s0 + 2 * t] = e0 + ex;
-            W.rstart[s0 + 2 * t] = e0 + ex;
-            W.rlen[s0 + 2 * t] = a0;
+            W.rsl[s0 + 2 * t] = make_int2((int32_t)(e0 + ex), a0);
         }
         if (2 * t + 1 < nr) {
             W.rowptr[s0 + 2 * t + 1] = e0 + ex + a0;
-            W.rstart[s0 + 2 * t + 1] = e0 + ex + a0;
-            W.rlen[s0 + 2 * t + 1] = a1;
+            W.rsl[s0 + 2 * t + 1] = make_int2((int32_t)(e0 + ex + a0), a1);
         }
     }
     if (g == nb * kTpSub - 1 && t == 0) W.rowptr[A.n] = A.nnz;
@@ -955,8 +962,9 @@ __global__ __launch_bounds__(256) void k_mrk_update(Csc A, Work W, int slot, int
     const int next = (slot + 1) % kSlots;
     for (int64_t f = blockIdx.x; f < nf; f += gridDim.x) {
         const int32_t m = W.flips[2 * f + 1];   // new mate column of the flipped row
-        const int64_t b = W.rstart[m];
-        const int32_t len = W.rlen[m];
+        const int2 rl = W.rsl[m];
+        const int64_t b = rl.x;
+        const int32_t len = rl.y;
         if (len > kHeavyRow) {  // block-uniform
             if (threadIdx.x == 0) W.heavy[atomicAdd(&W.counters[slot_word(slot, kHeavy)], 1)] = m;
             continue;
@@ -975,7 +983,8 @@ __global__ __launch_bounds__(256) void k_mrk_update_heavy(Csc A, Work W, int slo
     // gridDim.y rows at a time, each over a row of blocks
     for (int32_t h = blockIdx.y; h < nh; h += gridDim.y) {
         const int32_t m = W.heavy[h];
-        const int64_t b = W.rstart[m], e = b + W.rlen[m];
+        const int2 rl = W.rsl[m];
+        const int64_t b = rl.x, e = b + rl.y;
         const int32_t row = W.mc[m];
         for (int64_t x = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < e; x += stride)
             refresh_entry(A, W, x, m, row, incremental, next);
@@ -1127,7 +1136,6 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.chunk_off = (int64_t*)take((N + 1) * 8);
     W.chunk_col = (int32_t*)take(max_chunks * 4);
     W.part_g = (double*)take(max_chunks * 8);
-    W.part_i = (int32_t*)take(max_chunks * 4);
     W.part_c = (int32_t*)take(max_chunks * 4);
     W.part_k = (int64_t*)take(max_chunks * 8);
     W.part_p = (int64_t*)take(max_chunks * 8);
@@ -1138,8 +1146,9 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.result = (double*)take(4 * 8);
     W.max_chunks = (int64_t)max_chunks;
     W.rowptr = (int64_t*)take((N + 1) * 8);
-    W.rstart = (int64_t*)take(N * 8);
-    W.rlen = (int32_t*)take(N * 4);
+    W.rsl = (int2*)take(N * 8);
+    W.cp32 = (int32_t*)take((N + 1) * 4);
+    W.pm = (int32_t*)take(N * 4);
     W.colidx = (int32_t*)take(Z * 4 + 128);
     W.cscpos = (int32_t*)take(Z * 4);
     W.mrk = (int32_t*)take(Z * 4 + 128);

@@ -1,22 +1,30 @@
 // HIP kernels of Steps A-C (arXiv 1801.09809, Section 5.3): for every root
 // column j, every row i > m_j of column j and its closing edge {m_j, m_i},
-// the gain of the alternating 4-cycle and the per-root winner.  Roots are
-// binned by size: a tile of lanes per short root, a wave per medium root, a
-// block per 1024-entry chunk of a long column.  Three probes of the closing
-// edge give identical results: binary search of column m_i, and the row list
-// of m_j from the matching-ordered transpose (per lane, or chunked).
+// the gain of the alternating 4-cycle and the per-root winner.
+//
+// Roots are binned by size: a tile of lanes per short root, a wave per
+// medium root, a block per 1024-entry chunk of a long column.  The closing
+// edge is probed by binary search of column m_i (probe 1) or, the GPU form of
+// the marking trick of Section 4, by testing m_i against the row list of m_j
+// from the matching-ordered transpose (probes 2-5).  Every probe gives the
+// same (hit, position), so results never depend on the choice.
+//
+// With the transposed lists the search reads no row indices at all: the rows
+// i > m_j of column j are exactly the positions after the matched entry
+// (rows increase along a column), whose position pm[j] is kept up to date by
+// the flips; each such entry's m_i is streamed from mrk; candidates are
+// keyed by position, and the winner's row is read once, when it is published.
 #include "hwpm_device.h"
 
 namespace hwpm {
 
 // ---------------------------------------------------------------------------
-// Steps A-C.  Short columns: a tile of T lanes per root column, lanes stride
-// over the column (coalesced row_idx reads), each probes its own closing
-// edge, the tile reduces to the Step-C winner with cross-lane shuffles.
+// Probe 1.  Short columns: a tile of T lanes per root column, lanes stride
+// over the column (coalesced row_idx reads), each probes its own closing edge
+// by binary search, the tile reduces to the Step-C winner with shuffles.
 
 template <int T>
-__global__ __launch_bounds__(256) void k_search_short(Csc A, Work W, int32_t long_threshold,
-                                                      int slot) {
+__global__ __launch_bounds__(256) void k_search_short(Csc A, Work W, int32_t long_threshold) {
     if (round_over(W)) return;
     const int lane = threadIdx.x & (T - 1);
     const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
@@ -26,26 +34,28 @@ __global__ __launch_bounds__(256) void k_search_short(Csc A, Work W, int32_t lon
     if (hi - lo > long_threshold) return;  // split kernel handles it
     const int32_t mj = W.mc[j];
     const double wmj = W.wm[j];
-    Cand b{0.0, INT32_MAX, -1, -1, -1};
+    Cand b{0.0, kNoPos, -1, -1};
     for (int64_t k = lo + lane; k < hi; k += T) try_entry(A, W, k, mj, wmj, b);
     reduce_best<T>(b);
-    if (lane == 0) publish(W, j, b, slot);
+    if (lane == 0) publish(A, W, j, b);
 }
 
+// ---------------------------------------------------------------------------
 // Long columns: each block takes kLongChunk entries of one column and writes
 // a partial winner; k_merge_long reduces the partials of each column.  With
 // the transposed lists and a row list of m_j of at most kLongHashMax entries
-// the block first stores that list in an LDS hash table (column -> list
-// position) and every probe is one lookup; otherwise each probe binary
-// searches row m_j in column m_i.
+// the block first stores that list in an LDS hash set (column -> list
+// position) and every probe is one lookup; otherwise (or if the set cannot
+// take the list) each probe binary-searches row m_j in column m_i.
 constexpr int kLongHashMax = 2048;
 constexpr int kLongHashSlots = 4096;
 constexpr int kLongPre = kLongChunk / 256;  // chunk entries per thread
+static_assert(kLongHashSlots >= 2 * kLongHashMax, "long-column hash set at most half full");
 
 __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dirty, int transposed) {
     __shared__ double sg[4];
-    __shared__ int32_t si[4], sc[4];
     __shared__ int64_t sk[4], sp[4];
+    __shared__ int32_t sc[4];
     __shared__ int32_t hk[kLongHashSlots], hv[kLongHashSlots];
     if (round_over(W)) return;
     const int32_t total = W.counters[kNumChunks];
@@ -59,56 +69,59 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
         const int64_t hi0 = A.col_ptr[j + 1];
         const int64_t hi = (lo + kLongChunk < hi0) ? lo + kLongChunk : hi0;
         const int32_t mj = W.mc[j];
-        const double wmj = W.wm[j];
-        Cand b{0.0, INT32_MAX, -1, -1, -1};
-        const int32_t rlen = transposed ? W.rlen[j] : INT32_MAX;
-        if (rlen <= kLongHashMax) {
-            // the chunk's entries (kLongPre per thread) are loaded before the
-            // table is built, so that both loads are in flight together
-            int32_t iq[kLongPre], mq[kLongPre];
+        // transposed: the chunk's entries after the matched one; else every
+        // entry, pruned by row below
+        const int64_t start = transposed ? ((int64_t)W.pm[j] + 1 > lo ? (int64_t)W.pm[j] + 1 : lo) : lo;
+        Cand b{0.0, kNoPos, -1, -1};
+        const int2 rl = transposed ? W.rsl[j] : make_int2(0, INT32_MAX);
+        bool hashed = start < hi && rl.y <= kLongHashMax;  // block-uniform
+        if (hashed) {
+            // the chunk's mate columns (kLongPre per thread) are loaded
+            // before the set is built, so that both loads are in flight together
+            int32_t mq[kLongPre];
 #pragma unroll
             for (int q = 0; q < kLongPre; ++q) {
                 const int64_t k = lo + threadIdx.x + 256 * q;
-                iq[q] = (k < hi) ? A.row_idx[k] : -1;
-                mq[q] = (k < hi) ? W.mrk[k] : -1;
+                mq[q] = (k >= start && k < hi) ? W.mrk[k] : -1;
             }
-            const int64_t rs = W.rstart[j];
             uint32_t size = 256;
-            while ((int32_t)size < 2 * rlen) size <<= 1;
+            while ((int32_t)size < 2 * rl.y) size <<= 1;
             const uint32_t mask = size - 1;
             for (uint32_t x = threadIdx.x; x < size; x += blockDim.x) hk[x] = -1;
             __syncthreads();
-            for (int32_t x = threadIdx.x; x < rlen; x += blockDim.x) {
-                const int32_t c = W.colidx[rs + x];
-                uint32_t h = hash_col(c, mask);
-                while (atomicCAS(&hk[h], -1, c) != -1) h = (h + 1) & mask;  // keys are distinct
-                hv[h] = x;
-            }
-            __syncthreads();
+            bool ok = true;
+            for (int32_t x = threadIdx.x; x < rl.y; x += blockDim.x)
+                ok &= hash_insert(hk, hv, W.colidx[rl.x + x], x, mask, LdsCas32{});
+            hashed = !__syncthreads_or(!ok);  // a list the set cannot take: binary search
+            if (hashed) {
 #pragma unroll
-            for (int q = 0; q < kLongPre; ++q) {
-                const int32_t i = iq[q], mi = mq[q];
-                if (i <= mj) continue;  // also the slots past the chunk (i = -1)
-                const int32_t qx = hash_find(hk, hv, mi, mask);
-                if (qx < 0) continue;
-                const int64_t k = lo + threadIdx.x + 256 * q;
-                const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + qx] : find_row(A.col_ptr, A.row_idx, mi, mj);
-                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
-                if (g > 0.0 && better(g, i, b.g, b.i)) {
-                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
+                for (int q = 0; q < kLongPre; ++q) {
+                    const int32_t mi = mq[q];
+                    if (mi < 0) continue;
+                    const int32_t qx = hash_find(hk, hv, mi, mask);
+                    if (qx < 0) continue;
+                    const int64_t k = lo + threadIdx.x + 256 * q;
+                    const int64_t p = W.cscpos ? (int64_t)W.cscpos[rl.x + qx] : find_row(A.col_ptr, A.row_idx, mi, mj);
+                    if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[j]), k, mi, p);
                 }
             }
-        } else {
+            __syncthreads();  // the set is rebuilt for the next chunk
+        }
+        if (!hashed && start < hi) {
             // four entries per thread, their binary searches in lockstep
             const int32_t step = blockDim.x;
-            for (int64_t k0 = lo + threadIdx.x; k0 < hi; k0 += 4 * (int64_t)step) {
-                int32_t iq[4], cq[4], rq[4];
+            for (int64_t k0 = start + threadIdx.x; k0 < hi; k0 += 4 * (int64_t)step) {
+                int32_t cq[4], rq[4];
                 int64_t pq[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     const int64_t k = k0 + (int64_t)q * step;
-                    iq[q] = (k < hi) ? A.row_idx[k] : -1;
-                    cq[q] = (k < hi && iq[q] > mj) ? (transposed ? W.mrk[k] : W.mr[iq[q]]) : -1;
+                    if (transposed) {
+                        cq[q] = (k < hi) ? W.mrk[k] : -1;
+                    } else {
+                        const int32_t i = (k < hi) ? A.row_idx[k] : -1;
+                        cq[q] = (i > mj) ? W.mr[i] : -1;
+                    }
                     rq[q] = mj;
                 }
                 find_row_x4(A.col_ptr, A.row_idx, cq, rq, pq);
@@ -116,32 +129,28 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
                 for (int q = 0; q < 4; ++q) {
                     if (pq[q] < 0) continue;
                     const int64_t k = k0 + (int64_t)q * step;
-                    const double g = (A.w[k] + A.w[pq[q]]) - (W.wm[cq[q]] + wmj);
-                    if (g > 0.0 && better(g, iq[q], b.g, b.i)) {
-                        b.g = g; b.i = iq[q]; b.c = cq[q]; b.k = k; b.p = pq[q];
-                    }
+                    offer(b, (A.w[k] + A.w[pq[q]]) - (W.wm[cq[q]] + W.wm[j]), k, cq[q], pq[q]);
                 }
             }
         }
         reduce_best<64>(b);
         if (lane == 0) {
-            sg[wave] = b.g; si[wave] = b.i; sc[wave] = b.c; sk[wave] = b.k; sp[wave] = b.p;
+            sg[wave] = b.g; sk[wave] = b.k; sc[wave] = b.c; sp[wave] = b.p;
         }
         __syncthreads();
         if (threadIdx.x == 0) {
             for (int u = 1; u < 4; ++u) {
-                if (better(sg[u], si[u], b.g, b.i)) {
-                    b.g = sg[u]; b.i = si[u]; b.c = sc[u]; b.k = sk[u]; b.p = sp[u];
+                if (better(sg[u], sk[u], b.g, b.k)) {
+                    b.g = sg[u]; b.k = sk[u]; b.c = sc[u]; b.p = sp[u];
                 }
             }
-            W.part_g[cid] = b.g; W.part_i[cid] = b.i; W.part_c[cid] = b.c;
-            W.part_k[cid] = b.k; W.part_p[cid] = b.p;
+            W.part_g[cid] = b.g; W.part_k[cid] = b.k; W.part_c[cid] = b.c; W.part_p[cid] = b.p;
         }
         __syncthreads();
     }
 }
 
-__global__ void k_merge_long(Work W, int slot, int only_dirty) {
+__global__ void k_merge_long(Csc A, Work W, int only_dirty) {
     if (round_over(W)) return;
     const int32_t nl = W.counters[kNumLong];
     for (int32_t q = blockIdx.x * blockDim.x + threadIdx.x; q < nl; q += gridDim.x * blockDim.x) {
@@ -149,92 +158,140 @@ __global__ void k_merge_long(Work W, int slot, int only_dirty) {
             if (W.dirty[W.long_list[q]] == 0) continue;
             W.dirty[W.long_list[q]] = 0;
         }
-        Cand b{0.0, INT32_MAX, -1, -1, -1};
+        Cand b{0.0, kNoPos, -1, -1};
         for (int64_t cid = W.chunk_off[q]; cid < W.chunk_off[q + 1]; ++cid) {
-            if (better(W.part_g[cid], W.part_i[cid], b.g, b.i)) {
-                b.g = W.part_g[cid]; b.i = W.part_i[cid]; b.c = W.part_c[cid];
-                b.k = W.part_k[cid]; b.p = W.part_p[cid];
+            if (better(W.part_g[cid], W.part_k[cid], b.g, b.k)) {
+                b.g = W.part_g[cid]; b.k = W.part_k[cid]; b.c = W.part_c[cid]; b.p = W.part_p[cid];
             }
         }
-        publish(W, W.long_list[q], b, slot);
+        publish(A, W, W.long_list[q], b);
     }
 }
 
-// Steps A-C with the transposed probe, the GPU form of the marking trick of
-// the sequential algorithm (Section 4): for root j the row list of m_j is
-// read once per tile (contiguous) and every probe m_i of the tile is tested
-// against it with T cross-lane rotations; the per-entry mate columns m_i are
-// streamed from mrk (no gather).  Rows longer than kRowRotate fall back to the
-// binary-search probe of column m_i.  Both give the same (hit, position).
+// ---------------------------------------------------------------------------
+// Probe 2: transposed lists, one entry per lane.  For root j the row list of
+// m_j is read once per tile (contiguous) and every probe m_i of the tile is
+// tested against it with T cross-lane rotations.  Rows longer than kRowRotate
+// fall back to the binary-search probe of column m_i.
 constexpr int kRowRotate = 64;
 
 template <int T>
-__global__ __launch_bounds__(256) void k_search_rows(Csc A, Work W, int32_t long_threshold,
-                                                     int slot) {
+__global__ __launch_bounds__(256) void k_search_rows(Csc A, Work W, int32_t long_threshold) {
     if (round_over(W)) return;
     const int lane = threadIdx.x & (T - 1);
     const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
     if (tile >= A.n) return;  // tile-uniform
     const int32_t j = (int32_t)tile;
-    const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
+    const int32_t lo = W.cp32[j], hi = W.cp32[j + 1];
     if (hi - lo > long_threshold) return;
-    const int32_t mj = W.mc[j];
-    const double wmj = W.wm[j];
-    const int64_t rs = W.rstart[j];
-    const int32_t rlen = W.rlen[j];
-    Cand b{0.0, INT32_MAX, -1, -1, -1};
-    if (rlen <= kRowRotate) {
+    const int32_t s0 = W.pm[j] + 1;  // rows i > m_j: the positions after the matched entry
+    const int2 rl = W.rsl[j];
+    Cand b{0.0, kNoPos, -1, -1};
+    if (rl.y <= kRowRotate) {
         // row list of m_j, T entries per lane-chunk; -1 never equals a column
-        int32_t cv0 = (lane < rlen) ? W.colidx[rs + lane] : -1;
-        for (int64_t kc = lo; kc < hi; kc += T) {
-            const int64_t k = kc + lane;
-            int32_t i = -1, mi = -1;
-            if (k < hi) {
-                i = A.row_idx[k];
-                if (i > mj) mi = W.mrk[k];
-            }
+        const int32_t cv0 = (lane < rl.y) ? W.colidx[rl.x + lane] : -1;
+        for (int32_t kc = s0; kc < hi; kc += T) {  // tile-uniform trip count
+            const int32_t k = kc + lane;
+            const int32_t mi = (k < hi) ? W.mrk[k] : -2;
             int32_t q = -1;
-            for (int32_t rc = 0; rc < rlen; rc += T) {
-                const int32_t cv = (rc == 0) ? cv0
-                                             : ((rc + lane < rlen) ? W.colidx[rs + rc + lane] : -1);
+            for (int32_t rc = 0; rc < rl.y; rc += T) {
+                const int32_t cv = (rc == 0) ? cv0 : ((rc + lane < rl.y) ? W.colidx[rl.x + rc + lane] : -1);
 #pragma unroll
                 for (int sft = 0; sft < T; ++sft) {
                     const int src = (lane + sft) & (T - 1);
-                    const int32_t v = __shfl(cv, src, T);
-                    if (mi >= 0 && v == mi) q = rc + src;
+                    if (__shfl(cv, src, T) == mi) q = rc + src;
                 }
             }
             if (q >= 0) {
-                const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + q] : find_row(A.col_ptr, A.row_idx, mi, mj);
-                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
-                if (g > 0.0 && better(g, i, b.g, b.i)) {
-                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
-                }
+                const int64_t p = W.cscpos ? (int64_t)W.cscpos[rl.x + q] : find_row(A.col_ptr, A.row_idx, mi, W.mc[j]);
+                if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[j]), k, mi, p);
             }
         }
     } else {
-        for (int64_t k = lo + lane; k < hi; k += T) {
-            const int32_t i = A.row_idx[k];
-            if (i <= mj) continue;
+        const int32_t mj = W.mc[j];
+        for (int32_t k = s0 + lane; k < hi; k += T) {
             const int32_t mi = W.mrk[k];
             const int64_t p = find_row(A.col_ptr, A.row_idx, mi, mj);
             if (p < 0) continue;
-            const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
-            if (g > 0.0 && better(g, i, b.g, b.i)) {
-                b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
-            }
+            offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[j]), k, mi, p);
         }
     }
     reduce_best<T>(b);
-    if (lane == 0) publish(W, j, b, slot);
+    if (lane == 0) publish(A, W, j, b);
 }
 
-// Steps A-C, transposed probe, chunked form: a tile of T lanes per root, each
-// lane holding E entries of column j (i, m_i) and E entries of the row list
-// of m_j, so one root of up to T*E entries in both lists is searched with all
-// of its loads independent (one memory round trip per stage), and every probe
-// is compared with the whole row list through T cross-lane exchanges.  Roots
-// with a longer column or row list go to the wave-per-root kernel.
+// ---------------------------------------------------------------------------
+// Roots a tile cannot hold go to the wave-per-root kernel through kSpread
+// sub-lists per round; sub-list s of a round holds at most `cap` roots, at
+// medium[s * cap ...).
+__device__ __forceinline__ void hand_off(const Work& W, int slot, int sub, int32_t cap, int32_t j, bool want) {
+    const int32_t q = wave_append(&W.counters[spread_word(slot, sub)], want);
+    if (want) W.medium[(int64_t)sub * cap + q] = j;
+}
+
+// Exchanges inside a tile of T lanes.  With 4-lane tiles they are DPP quad
+// permutations (a VALU move, no trip through the LDS crossbar).
+template <int T>
+__device__ __forceinline__ int32_t tile_xor(int32_t v, int sft) {
+    if constexpr (T == 4) {
+        switch (sft) {
+            case 0: return v;
+            case 1: return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+            case 2: return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+            default: return __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, false);  // quad_perm [3,2,1,0]
+        }
+    } else {
+        return __shfl_xor(v, sft, T);
+    }
+}
+
+template <int T>
+__device__ __forceinline__ int32_t tile_bcast(int32_t v, int src) {
+    if constexpr (T == 4) {
+        switch (src) {
+            case 0: return __builtin_amdgcn_mov_dpp(v, 0x00, 0xF, 0xF, false);  // quad_perm [0,0,0,0]
+            case 1: return __builtin_amdgcn_mov_dpp(v, 0x55, 0xF, 0xF, false);  // quad_perm [1,1,1,1]
+            case 2: return __builtin_amdgcn_mov_dpp(v, 0xAA, 0xF, 0xF, false);  // quad_perm [2,2,2,2]
+            default: return __builtin_amdgcn_mov_dpp(v, 0xFF, 0xF, 0xF, false);  // quad_perm [3,3,3,3]
+        }
+    } else {
+        return __shfl(v, src, T);
+    }
+}
+
+// Largest value over the wave, as a wave-uniform (scalar) value.
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// The per-root values of a tile kernel, read together (one memory round trip).
+struct RootView {
+    int32_t j, s0, slen;  // root, first position after the matched entry, suffix length
+    int2 rl;              // row list of m_j: (start, length)
+    bool own;             // a short root of this kernel (long columns: the split kernel)
+};
+
+__device__ __forceinline__ RootView load_root(const Work& W, int64_t t, int64_t ntiles, const int32_t* roots,
+                                              int32_t long_threshold) {
+    RootView r;
+    const bool in = t < ntiles;
+    r.j = in ? (roots ? roots[t] : (int32_t)t) : 0;
+    const int32_t lo = W.cp32[r.j], hi = W.cp32[r.j + 1], pmj = W.pm[r.j];
+    r.rl = W.rsl[r.j];
+    r.own = in && hi - lo <= long_threshold;
+    r.s0 = pmj + 1;  // rows i > m_j: the positions after the matched entry
+    r.slen = r.own ? hi - r.s0 : 0;
+    return r;
+}
+
+// Probe 4: transposed lists, cross-lane form: a tile of T lanes per root,
+// each lane holding E entries of the pruned suffix of column j (their m_i)
+// and E entries of the row list of m_j, every probe compared with the whole
+// row list through T cross-lane exchanges.  The comparisons stop at the
+// longest suffix and row list of the wave.  Roots with a longer suffix or row
+// list than T * E are handed off.
 template <int T, int E>
 __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t long_threshold,
                                                       int slot, const int32_t* __restrict__ roots,
@@ -244,92 +301,157 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
     // roots: this round's list (its length on the device; the grid covers
     // every column), else every column
     const int64_t ntiles = roots ? W.counters[slot_word(slot, kRoots)] : A.n;
-    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
-    if (tile >= ntiles) return;  // tile-uniform
-    const int32_t j = roots ? roots[tile] : (int32_t)tile;
-    // the root's values are read with its column bounds: one memory round
-    // trip instead of two (wasted for the roots that return below).  The
-    // empty asm statement takes all six as inputs, so the compiler issues
-    // the six loads before it instead of sinking four of them past the
-    // branches below (after the bounds' wait).
-    const int32_t mj = W.mc[j];
-    const double wmj = W.wm[j];
-    const int64_t rs = W.rstart[j];
-    const int32_t rlen = W.rlen[j];
-    const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
-    asm volatile("" ::"v"(mj), "v"(wmj), "v"(rs), "v"(rlen), "v"(lo), "v"(hi));
-    const int64_t len = hi - lo;
-    if (len > long_threshold) return;  // split kernel handles it
-    if (roots && lane == 0) W.dirty[j] = 0;
-    Cand b{0.0, INT32_MAX, -1, -1, -1};
-    if (len > 1) {  // a single entry is the matched one: no cycle
-        // a root too long for the tile goes to the wave-per-root kernel
-        const bool handoff = len > T * E || rlen > T * E;
-        const int sub = blockIdx.x & (kSpread - 1);
-        const int32_t q = wave_append(&W.counters[spread_word(slot, sub)], handoff && lane == 0);
-        if (handoff) {
-            if (lane == 0) W.medium[(int64_t)sub * cap + q] = j;
-            return;  // tile-uniform
-        }
-        {
-            int32_t iv[E], mv[E], rv[E];
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
+    if (((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63)) / T >= ntiles) return;  // wave-uniform
+    const RootView r = load_root(W, t, ntiles, roots, long_threshold);
+    if (r.own && roots && lane == 0) W.dirty[r.j] = 0;
+    const bool handoff = r.slen > 0 && (r.slen > T * E || r.rl.y > T * E);
+    hand_off(W, slot, blockIdx.x & (kSpread - 1), cap, r.j, handoff && lane == 0);
+    const bool search = r.slen > 0 && !handoff;
+    int32_t mv[E], rv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int32_t x = lane + T * e;
+        mv[e] = (search && x < r.slen) ? W.mrk[r.s0 + x] : -1;
+        rv[e] = (search && x < r.rl.y) ? W.colidx[r.rl.x + x] : -2;  // -1 / -2 never match each other
+    }
+    const int32_t e_lim = (wave_max(search ? r.slen : 0) + T - 1) / T;
+    const int32_t f_lim = (wave_max(search ? r.rl.y : 0) + T - 1) / T;
+    int32_t qv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) qv[e] = -1;
+#pragma unroll
+    for (int sft = 0; sft < T; ++sft) {
+#pragma unroll
+        for (int f = 0; f < E; ++f) {
+            if (f >= f_lim) break;  // wave-uniform
+            const int32_t v = tile_xor<T>(rv[f], sft);
+            const int32_t x = (lane ^ sft) + T * f;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const int64_t k = lo + lane + T * e;
-                iv[e] = (k < hi) ? A.row_idx[k] : -1;
-                const int32_t x = lane + T * e;
-                rv[e] = (x < rlen) ? W.colidx[rs + x] : -1;
-            }
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int64_t k = lo + lane + T * e;
-                mv[e] = (iv[e] > mj) ? W.mrk[k] : -1;
-            }
-            int32_t qv[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e) qv[e] = -1;
-#pragma unroll
-            for (int sft = 0; sft < T; ++sft) {
-#pragma unroll
-                for (int f = 0; f < E; ++f) {
-                    const int32_t v = __shfl_xor(rv[f], sft, T);
-                    const int32_t x = (lane ^ sft) + T * f;
-#pragma unroll
-                    for (int e = 0; e < E; ++e)
-                        if (mv[e] >= 0 && v == mv[e]) qv[e] = x;
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                if (qv[e] >= 0) {
-                    const int64_t k = lo + lane + T * e;
-                    const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + qv[e]] : find_row(A.col_ptr, A.row_idx, mv[e], mj);
-                    const double g = (A.w[k] + A.w[p]) - (W.wm[mv[e]] + wmj);
-                    if (g > 0.0 && better(g, iv[e], b.g, b.i)) {
-                        b.g = g; b.i = iv[e]; b.c = mv[e]; b.k = k; b.p = p;
-                    }
-                }
+                if (e >= e_lim) break;  // wave-uniform
+                if (v == mv[e]) qv[e] = x;
             }
         }
     }
-    reduce_best<T>(b);
-    if (lane == 0) publish(W, j, b, slot);
+    Cand b{0.0, kNoPos, -1, -1};
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (qv[e] >= 0) {
+            const int32_t k = r.s0 + lane + T * e;
+            const int64_t p = W.cscpos ? (int64_t)W.cscpos[r.rl.x + qv[e]] : find_row(A.col_ptr, A.row_idx, mv[e], W.mc[r.j]);
+            if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mv[e]] + W.wm[r.j]), k, mv[e], p);
+        }
+    }
+    if (__ballot(b.k != kNoPos)) reduce_best<T>(b);  // wave-uniform: most waves have no candidate
+    if (r.own && !handoff && lane == 0) publish(A, W, r.j, b);
 }
 
-// Steps A-C for the roots a tile cannot hold (a column or a row list longer
-// than T*E): one wave per root.  When the row list of m_j has at most
-// kHashMax entries the wave stores it in an LDS hash table (column -> list
+// Probes 3 and 5: transposed lists, filter form (the default).  A tile of T
+// lanes per root loads the pruned suffix of column j (E mate columns per
+// lane) and the row list of m_j (E columns per lane), all loads independent.
+// The tile ORs its row list into a two-word filter (one bit per word, from
+// two multiplicative hashes of the column), and each probe m_i whose two bits
+// are both set is compared exactly with the whole row list, gathered once
+// into every lane of the tile; the others are certain misses.  With about 17
+// columns in a row list a miss passes the filter about 5 % of the time, so
+// on matrices whose probes mostly miss the exact comparisons shrink from
+// every pair to a few probes per wave.  Roots whose suffix or row list
+// exceeds T * E entries are handed off.
+__device__ __forceinline__ uint32_t filter_bit1(int32_t c) { return ((uint32_t)c * 0x9E3779B1u) >> 26; }
+__device__ __forceinline__ uint32_t filter_bit2(int32_t c) { return ((uint32_t)c * 0x85EBCA6Bu) >> 26; }
+
+template <int T, int E>
+__global__ __launch_bounds__(256) void k_search_filter(Csc A, Work W, int32_t long_threshold, int slot,
+                                                       const int32_t* __restrict__ roots, int32_t cap) {
+    if (round_over(W)) return;
+    const int lane = threadIdx.x & (T - 1);
+    const int64_t ntiles = roots ? W.counters[slot_word(slot, kRoots)] : A.n;
+    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
+    if (((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63)) / T >= ntiles) return;  // wave-uniform
+    const RootView r = load_root(W, t, ntiles, roots, long_threshold);
+    if (r.own && roots && lane == 0) W.dirty[r.j] = 0;
+    const bool handoff = r.slen > 0 && (r.slen > T * E || r.rl.y > T * E);
+    hand_off(W, slot, blockIdx.x & (kSpread - 1), cap, r.j, handoff && lane == 0);
+    const bool search = r.slen > 0 && !handoff;
+    // loads: indices clamped into the segment (the matched entry and the
+    // list's first entry always exist), values past it masked
+    int32_t mv[E], rv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int32_t x = lane + T * e;
+        mv[e] = W.mrk[x < r.slen ? r.s0 + x : r.s0 - 1];
+        rv[e] = W.colidx[x < r.rl.y ? r.rl.x + x : r.rl.x];
+    }
+    uint32_t f1lo = 0, f1hi = 0, f2lo = 0, f2hi = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int32_t x = lane + T * e;
+        if (!(search && x < r.slen)) mv[e] = -1;
+        if (!(search && x < r.rl.y)) rv[e] = -2;
+        if (rv[e] >= 0) {
+            const uint32_t b1 = filter_bit1(rv[e]), b2 = filter_bit2(rv[e]);
+            if (b1 < 32) f1lo |= 1u << b1; else f1hi |= 1u << (b1 - 32);
+            if (b2 < 32) f2lo |= 1u << b2; else f2hi |= 1u << (b2 - 32);
+        }
+    }
+#pragma unroll
+    for (int sft = 1; sft < T; sft <<= 1) {
+        f1lo |= (uint32_t)tile_xor<T>((int32_t)f1lo, sft);
+        f1hi |= (uint32_t)tile_xor<T>((int32_t)f1hi, sft);
+        f2lo |= (uint32_t)tile_xor<T>((int32_t)f2lo, sft);
+        f2hi |= (uint32_t)tile_xor<T>((int32_t)f2hi, sft);
+    }
+    uint32_t pending = 0;  // bit e: probe e passed the filter
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (mv[e] < 0) continue;
+        const uint32_t b1 = filter_bit1(mv[e]), b2 = filter_bit2(mv[e]);
+        const uint32_t w1 = b1 < 32 ? f1lo : f1hi, w2 = b2 < 32 ? f2lo : f2hi;
+        if ((w1 >> (b1 & 31)) & (w2 >> (b2 & 31)) & 1u) pending |= 1u << e;
+    }
+    Cand b{0.0, kNoPos, -1, -1};
+    if (__ballot(pending != 0)) {  // wave-uniform
+        // the tile's whole row list in every lane: place x = src + T * f
+        int32_t all[T * E];
+#pragma unroll
+        for (int f = 0; f < E; ++f)
+#pragma unroll
+            for (int src = 0; src < T; ++src) all[src + T * f] = tile_bcast<T>(rv[f], src);
+        while (__ballot(pending != 0)) {  // wave-uniform: one passed probe per lane at a time
+            const int e = pending ? __builtin_ctz(pending) : -1;
+            pending &= pending - 1;
+            int32_t mi = -1;
+#pragma unroll
+            for (int u = 0; u < E; ++u)
+                if (u == e) mi = mv[u];
+            int32_t q = -1;
+#pragma unroll
+            for (int x = 0; x < T * E; ++x)
+                if (all[x] == mi) q = x;
+            if (q >= 0) {
+                const int32_t k = r.s0 + lane + T * e;
+                const int64_t p = W.cscpos ? (int64_t)W.cscpos[r.rl.x + q] : find_row(A.col_ptr, A.row_idx, mi, W.mc[r.j]);
+                if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[r.j]), k, mi, p);
+            }
+        }
+    }
+    if (__ballot(b.k != kNoPos)) reduce_best<T>(b);  // wave-uniform: most waves have no candidate
+    if (r.own && !handoff && lane == 0) publish(A, W, r.j, b);
+}
+
+// ---------------------------------------------------------------------------
+// Steps A-C for the roots a tile cannot hold (a pruned suffix or a row list
+// longer than the tile): one wave per root.  When the row list of m_j has at
+// most kHashMax entries the wave stores it in an LDS hash set (column -> list
 // position) and every probe m_i is one lookup (the marking trick of Section 4
-// with a hash set for the mark array); longer lists take the binary search of
-// row m_j in column m_i.  The 64 lanes stride over the column.
+// with a hash set for the mark array); longer lists, or a list the set cannot
+// take, use the binary search of row m_j in column m_i.  The 64 lanes stride
+// over the suffix of the column.
 constexpr int kHashMax = 512;       // row-list entries a wave hashes
-constexpr int kHashSlots = 1024;    // table size per wave (load factor <= 1/2)
+constexpr int kHashSlots = 1024;    // set size per wave (load factor <= 1/2)
 constexpr int kHashPre = 4;         // column entries per lane loaded up front
-
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
+static_assert(kHashSlots >= 2 * kHashMax, "wave hash set at most half full");
 
 __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot, int32_t cap) {
     __shared__ int32_t keys[4][kHashSlots];
@@ -356,161 +478,69 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot, 
         const int sub = (int)__popcll(__ballot(incl <= item));
         const int32_t at = item - __shfl(incl - len_s, sub, 64);
         const int32_t j = W.medium[(int64_t)sub * cap + at];
-        const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
-        const int32_t mj = W.mc[j];
-        const double wmj = W.wm[j];
-        const int64_t rs = W.rstart[j];
-        const int32_t rlen = W.rlen[j];
-        Cand b{0.0, INT32_MAX, -1, -1, -1};
-        if (rlen <= kHashMax) {
-            // the column's entries (at most 256: longer columns are split)
-            // are loaded before the table is built, so that both loads are in
-            // flight together
-            int32_t iq[kHashPre], mq[kHashPre];
+        const int32_t hi = W.cp32[j + 1];
+        const int32_t s0 = W.pm[j] + 1;  // rows i > m_j: positions after the matched entry
+        const int2 rl = W.rsl[j];
+        Cand b{0.0, kNoPos, -1, -1};
+        bool hashed = rl.y <= kHashMax;  // wave-uniform
+        if (hashed) {
+            // the suffix's first entries (at most 256 entries in all: longer
+            // columns are split) are loaded before the set is built, so that
+            // both loads are in flight together
+            int32_t mq[kHashPre];
 #pragma unroll
             for (int q = 0; q < kHashPre; ++q) {
-                const int64_t k = lo + lane + 64 * q;
-                iq[q] = (k < hi) ? A.row_idx[k] : -1;
+                const int32_t k = s0 + lane + 64 * q;
                 mq[q] = (k < hi) ? W.mrk[k] : -1;
             }
             uint32_t size = 64;
-            while ((int32_t)size < 2 * rlen) size <<= 1;
+            while ((int32_t)size < 2 * rl.y) size <<= 1;
             const uint32_t mask = size - 1;
             wave_lds_sync();  // the previous root's lookups are done
             for (uint32_t x = lane; x < size; x += 64) hk[x] = -1;
             wave_lds_sync();
-            for (int32_t x = lane; x < rlen; x += 64) {
-                const int32_t c = W.colidx[rs + x];
-                uint32_t h = hash_col(c, mask);
-                while (atomicCAS(&hk[h], -1, c) != -1) h = (h + 1) & mask;  // keys are distinct
-                hv[h] = x;
-            }
+            bool ok = true;
+            for (int32_t x = lane; x < rl.y; x += 64)
+                ok &= hash_insert(hk, hv, W.colidx[rl.x + x], x, mask, LdsCas32{});
             wave_lds_sync();
-            auto probe = [&](int64_t k, int32_t i, int32_t mi) {
-                if (i <= mj) return;
-                const int32_t qx = hash_find(hk, hv, mi, mask);
-                if (qx < 0) return;
-                const int64_t p = W.cscpos ? (int64_t)W.cscpos[rs + qx] : find_row(A.col_ptr, A.row_idx, mi, mj);
-                const double g = (A.w[k] + A.w[p]) - (W.wm[mi] + wmj);
-                if (g > 0.0 && better(g, i, b.g, b.i)) {
-                    b.g = g; b.i = i; b.c = mi; b.k = k; b.p = p;
-                }
-            };
+            hashed = __ballot(!ok) == 0ull;
+            if (hashed) {
+                auto probe = [&](int32_t k, int32_t mi) {
+                    const int32_t qx = hash_find(hk, hv, mi, mask);
+                    if (qx < 0) return;
+                    const int64_t p = W.cscpos ? (int64_t)W.cscpos[rl.x + qx] : find_row(A.col_ptr, A.row_idx, mi, W.mc[j]);
+                    if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[j]), k, mi, p);
+                };
 #pragma unroll
-            for (int q = 0; q < kHashPre; ++q)
-                if (iq[q] >= 0) probe(lo + lane + 64 * q, iq[q], mq[q]);
-            for (int64_t k = lo + 64 * kHashPre + lane; k < hi; k += 64) probe(k, A.row_idx[k], W.mrk[k]);
-        } else {
+                for (int q = 0; q < kHashPre; ++q)
+                    if (mq[q] >= 0) probe(s0 + lane + 64 * q, mq[q]);
+                for (int32_t k = s0 + 64 * kHashPre + lane; k < hi; k += 64) probe(k, W.mrk[k]);
+            }
+        }
+        if (!hashed) {
             // four entries per lane, their binary searches in lockstep
-            for (int64_t k0 = lo + lane; k0 < hi; k0 += 4 * 64) {
-                int32_t iq[4], cq[4], rq[4];
+            const int32_t mj = W.mc[j];
+            for (int32_t k0 = s0 + lane; k0 < hi; k0 += 4 * 64) {
+                int32_t cq[4], rq[4];
                 int64_t pq[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int64_t k = k0 + 64 * q;
-                    iq[q] = (k < hi) ? A.row_idx[k] : -1;
-                    cq[q] = (k < hi && iq[q] > mj) ? W.mrk[k] : -1;
+                    const int32_t k = k0 + 64 * q;
+                    cq[q] = (k < hi) ? W.mrk[k] : -1;
                     rq[q] = mj;
                 }
                 find_row_x4(A.col_ptr, A.row_idx, cq, rq, pq);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     if (pq[q] < 0) continue;
-                    const int64_t k = k0 + 64 * q;
-                    const double g = (A.w[k] + A.w[pq[q]]) - (W.wm[cq[q]] + wmj);
-                    if (g > 0.0 && better(g, iq[q], b.g, b.i)) {
-                        b.g = g; b.i = iq[q]; b.c = cq[q]; b.k = k; b.p = pq[q];
-                    }
+                    const int32_t k = k0 + 64 * q;
+                    offer(b, (A.w[k] + A.w[pq[q]]) - (W.wm[cq[q]] + W.wm[j]), k, cq[q], pq[q]);
                 }
             }
         }
         reduce_best<64>(b);
-        if (lane == 0) publish(W, j, b, slot);
+        if (lane == 0) publish(A, W, j, b);
     }
-}
-
-// Steps A-C, transposed probe, vector form: a quad of lanes per root; each
-// stream (row indices, mate columns, the row list of m_j) is read as the
-// 32-entry window that starts at the 16-byte boundary below the segment, one
-// 16-byte load per lane and half, all independent.  Entries outside the
-// segment are masked.  A segment that does not fit its window (or a window
-// that would pass the end of row_idx) takes the generic path.
-__device__ __forceinline__ int4 ld4(const int32_t* p) { return *reinterpret_cast<const int4*>(p); }
-
-__global__ __launch_bounds__(256) void k_search_vec(Csc A, Work W, int32_t long_threshold, int slot,
-                                                    const int32_t* __restrict__ roots, int32_t cap) {
-    constexpr int T = 4, E = 8;
-    if (round_over(W)) return;
-    const int lane = threadIdx.x & 3;
-    const int64_t ntiles = roots ? W.counters[slot_word(slot, kRoots)] : A.n;
-    const int64_t tile = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
-    if (tile >= ntiles) return;  // tile-uniform
-    const int32_t j = roots ? roots[tile] : (int32_t)tile;
-    // the root's values are read with its column bounds (as in k_search_chunk)
-    const int32_t mj = W.mc[j];
-    const double wmj = W.wm[j];
-    const int64_t rs = W.rstart[j];
-    const int32_t rlen = W.rlen[j];
-    const int64_t lo = A.col_ptr[j], hi = A.col_ptr[j + 1];
-    asm volatile("" ::"v"(mj), "v"(wmj), "v"(rs), "v"(rlen), "v"(lo), "v"(hi));
-    const int64_t len = hi - lo;
-    if (len > long_threshold) return;  // split kernel handles it
-    if (roots && lane == 0) W.dirty[j] = 0;
-    Cand b{0.0, INT32_MAX, -1, -1, -1};
-    if (len > 1) {
-        const int64_t cb = lo & ~(int64_t)3, rb = rs & ~(int64_t)3;
-        // a segment that does not fit its window goes to the wave-per-root kernel
-        const bool handoff = !(hi <= cb + 32 && rs + rlen <= rb + 32 && cb + 32 <= A.nnz);
-        const int sub = blockIdx.x & (kSpread - 1);
-        const int32_t q = wave_append(&W.counters[spread_word(slot, sub)], handoff && lane == 0);
-        if (handoff) {
-            if (lane == 0) W.medium[(int64_t)sub * cap + q] = j;
-            return;  // tile-uniform
-        }
-        {
-            const int4 i0 = ld4(A.row_idx + cb + 4 * lane), i1 = ld4(A.row_idx + cb + 16 + 4 * lane);
-            const int4 m0 = ld4(W.mrk + cb + 4 * lane), m1 = ld4(W.mrk + cb + 16 + 4 * lane);
-            const int4 r0 = ld4(W.colidx + rb + 4 * lane), r1 = ld4(W.colidx + rb + 16 + 4 * lane);
-            int32_t iv[E] = {i0.x, i0.y, i0.z, i0.w, i1.x, i1.y, i1.z, i1.w};
-            int32_t mv[E] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
-            int32_t rv[E] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                const int64_t k = cb + 16 * (e >> 2) + 4 * lane + (e & 3);
-                const bool in = k >= lo && k < hi;
-                if (!(in && iv[e] > mj)) mv[e] = -1;
-                const int64_t x = rb + 16 * (e >> 2) + 4 * lane + (e & 3);
-                if (x < rs || x >= rs + rlen) rv[e] = -1;
-            }
-            int32_t qv[E];
-#pragma unroll
-            for (int e = 0; e < E; ++e) qv[e] = -1;
-#pragma unroll
-            for (int sft = 0; sft < T; ++sft) {
-#pragma unroll
-                for (int f = 0; f < E; ++f) {
-                    const int32_t v = __shfl_xor(rv[f], sft, T);
-                    const int32_t x = 16 * (f >> 2) + 4 * (lane ^ sft) + (f & 3);
-#pragma unroll
-                    for (int e = 0; e < E; ++e)
-                        if (mv[e] >= 0 && v == mv[e]) qv[e] = x;
-                }
-            }
-#pragma unroll
-            for (int e = 0; e < E; ++e) {
-                if (qv[e] >= 0) {
-                    const int64_t k = cb + 16 * (e >> 2) + 4 * lane + (e & 3);
-                    const int64_t p = W.cscpos ? (int64_t)W.cscpos[rb + qv[e]] : find_row(A.col_ptr, A.row_idx, mv[e], mj);
-                    const double g = (A.w[k] + A.w[p]) - (W.wm[mv[e]] + wmj);
-                    if (g > 0.0 && better(g, iv[e], b.g, b.i)) {
-                        b.g = g; b.i = iv[e]; b.c = mv[e]; b.k = k; b.p = p;
-                    }
-                }
-            }
-        }
-    }
-    reduce_best<T>(b);
-    if (lane == 0) publish(W, j, b, slot);
 }
 
 hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t long_threshold,
@@ -521,23 +551,28 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
     const int64_t all_blocks = ((int64_t)A.n * tile_width + 255) / 256;
     const unsigned blocks = (unsigned)(all_blocks > 0 ? all_blocks : 1);
     const int32_t* roots = listed ? W.dirty_list : nullptr;
-    const bool transposed = probe == 2;
-#define HWPM_SEARCH(TW)                                                                     \
-    if (transposed)                                                                         \
-        hipLaunchKernelGGL(k_search_rows<TW>, dim3(blocks), dim3(256), 0, s, A, W,          \
-                           long_threshold, slot);                                           \
-    else                                                                                    \
-        hipLaunchKernelGGL(k_search_short<TW>, dim3(blocks), dim3(256), 0, s, A, W,         \
-                           long_threshold, slot);
-    // hand-off sub-list capacity: the roots of the blocks that share a
-    // sub-list (kSpread sub-lists hold at most n + 4095 roots in all)
     int32_t cap = 0;
-    if (probe == 4) {
-        const int64_t vall = ((int64_t)A.n * 4 + 255) / 256;
-        const unsigned vblocks = (unsigned)(vall > 0 ? vall : 1);
-        cap = (int32_t)((vblocks + kSpread - 1) / kSpread * (256 / 4));
-        hipLaunchKernelGGL(k_search_vec, dim3(vblocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap);
-    } else if (probe == 3) {
+    if (probe == 1) {
+        switch (tile_width) {
+            case 4: hipLaunchKernelGGL(k_search_short<4>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            case 8: hipLaunchKernelGGL(k_search_short<8>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            case 16: hipLaunchKernelGGL(k_search_short<16>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            case 32: hipLaunchKernelGGL(k_search_short<32>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            case 64: hipLaunchKernelGGL(k_search_short<64>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (probe == 2) {
+        switch (tile_width) {
+            case 4: hipLaunchKernelGGL(k_search_rows<4>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            case 8: hipLaunchKernelGGL(k_search_rows<8>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            case 16: hipLaunchKernelGGL(k_search_rows<16>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            case 32: hipLaunchKernelGGL(k_search_rows<32>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            case 64: hipLaunchKernelGGL(k_search_rows<64>, dim3(blocks), dim3(256), 0, s, A, W, long_threshold); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else if (probe == 4) {
+        // hand-off sub-lists by block: the roots of the blocks that share a
+        // sub-list (kSpread sub-lists hold at most n + 4095 roots in all)
         cap = (int32_t)((blocks + kSpread - 1) / kSpread * (256 / tile_width));
         switch (tile_width) {
             case 4: hipLaunchKernelGGL((k_search_chunk<4, 8>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
@@ -546,15 +581,16 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
             case 32: hipLaunchKernelGGL((k_search_chunk<32, 1>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
             default: return hipErrorInvalidValue;
         }
-    } else switch (tile_width) {
-        case 4: HWPM_SEARCH(4) break;
-        case 8: HWPM_SEARCH(8) break;
-        case 16: HWPM_SEARCH(16) break;
-        case 32: HWPM_SEARCH(32) break;
-        case 64: HWPM_SEARCH(64) break;
-        default: return hipErrorInvalidValue;
+    } else {  // probes 3 and 5 (the row lists with or without positions)
+        cap = (int32_t)((blocks + kSpread - 1) / kSpread * (256 / tile_width));
+        switch (tile_width) {
+            case 4: hipLaunchKernelGGL((k_search_filter<4, 8>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+            case 8: hipLaunchKernelGGL((k_search_filter<8, 4>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+            case 16: hipLaunchKernelGGL((k_search_filter<16, 2>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+            case 32: hipLaunchKernelGGL((k_search_filter<32, 1>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+            default: return hipErrorInvalidValue;
+        }
     }
-#undef HWPM_SEARCH
     if (probe >= 3) hipLaunchKernelGGL(k_search_medium, dim3(cus * 8), dim3(256), 0, s, A, W, slot, cap);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !has_long) return e;
@@ -562,7 +598,7 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
     hipLaunchKernelGGL(k_search_long, dim3(cus * 8), dim3(256), 0, s, A, W, only_dirty, probe >= 2 ? 1 : 0);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_merge_long, dim3(64), dim3(256), 0, s, W, slot, only_dirty);
+    hipLaunchKernelGGL(k_merge_long, dim3(64), dim3(256), 0, s, A, W, only_dirty);
     return hipGetLastError();
 }
 

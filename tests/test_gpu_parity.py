@@ -118,9 +118,7 @@ def test_random_vs_oracle(solver, n, d, seed, intw, probe):
 @pytest.mark.parametrize("tile", [4, 8, 16, 32, 64])
 def test_tile_widths_identical(solver, tile, probe):
     if probe[:2] in ("p3", "p4", "p5") and tile == 64:
-        pytest.skip("the chunked kernel takes tiles of 4 to 32 lanes")
-    if probe[:2] == "p4" and tile != 4:
-        pytest.skip("the vector kernel always uses 4-lane tiles")
+        pytest.skip("the row-list tile kernels take tiles of 4 to 32 lanes")
     wl = workload(0)
     run_both(solver, wl, tile_width=tile, **_PROBE_KW[probe])
     wl2 = small_random(5003, 30, 77, integer_weights=True, weight_range=1)  # heavy ties
@@ -378,6 +376,49 @@ def test_full_rmat_first_rounds_bit_exact(solver, probe):
     assert_same(wl, gpu, ref)
 
 
+def _golden_rmat():
+    with open(os.path.join(GOLDEN, "rmat_scale22_converged.json")) as f:
+        return json.load(f)
+
+
+def _digest(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def _first_round_diff(got, want):
+    for r, (g, w) in enumerate(zip(got, want)):
+        if g != w:
+            return r
+    return None if len(got) == len(want) else min(len(got), len(want))
+
+
+@pytest.mark.parametrize("probe,cap", [("p3", 0), ("p3full", 0), ("p5", 0), ("p4", 0), ("p3", 10)])
+def test_full_rmat_vs_oracle_golden(solver, probe, cap):
+    """R-MAT scale 22 solved from its planted matching (119 rounds to
+    convergence, and the paper's cap of 10) against the oracle's stored
+    result (tests/golden/make_rmat_golden.py runs the oracle alone): the
+    permutation's digest, the totals' bit patterns and every round's
+    candidate and flip counts."""
+    gold = _golden_rmat()
+    wl, (perm, total, st) = _full(solver, 3, max_rounds=cap, probe=probe)
+    assert (wl.n, wl.nnz) == (gold["n"], gold["nnz"])
+    for name, arr in (("col_ptr", wl.col_ptr), ("row_idx", wl.row_idx), ("w", wl.w), ("planted", wl.planted)):
+        assert _digest(arr) == gold["input_sha256"][name], f"regenerated {name} differs from the recorded input"
+    ref = gold["converged" if cap == 0 else "maxiters_10"]
+    rounds = ref["rounds"]
+    cand, flips = st["round_candidates"][:rounds], st["round_applied"][:rounds]
+    r = _first_round_diff(cand, ref["round_candidates"])
+    assert r is None, f"round {r}: {cand[r] if r < len(cand) else None} candidates, oracle {ref['round_candidates'][r]}"
+    r = _first_round_diff(flips, ref["round_applied"])
+    assert r is None, f"round {r}: {flips[r] if r < len(flips) else None} flips, oracle {ref['round_applied'][r]}"
+    assert st["rounds"] == rounds and st["hit_round_cap"] == int(ref["hit_round_cap"])
+    assert st["cycles_applied"] == ref["cycles_applied"]
+    assert np.float64(st["init_weight"]).tobytes()[::-1].hex() == ref["init_weight_bits"]
+    assert np.float64(total).tobytes()[::-1].hex() == ref["total_bits"]
+    assert _digest(perm.astype(np.int32)) == ref["perm_sha256"]
+
+
 def test_full_rmat_converged_properties(solver):
     wl, (perm, total, st) = _full(solver, 3, probe="p3")  # default: incremental rounds
     _, other = _full(solver, 3, probe="p3full")
@@ -416,8 +457,11 @@ def match_both(solver, wl, plain=False, **kw):
     gpu = gpu_match(solver, wl, mcm_plain=plain, **kw)
     assert_same(wl, gpu, ref)
     st = gpu[2]
-    assert st["greedy_cardinality"] == gcard
+    assert st["greedy_cardinality"] == gcard == ref.greedy_cardinality
     assert st["mcm_cardinality"] == ref.mcm_cardinality == wl.n
+    # Phase I step counts: proposal rounds, BFS phases and levels
+    assert (st["greedy_rounds"], st["mcm_phases"], st["mcm_levels"]) == \
+        (ref.greedy_rounds, ref.mcm_phases, ref.mcm_levels)
     return gpu, ref
 
 

@@ -123,6 +123,12 @@ typedef struct {
      * the results are identical.  1 = every round searches every column (the
      * paper's rounds as written; the benchmark's search-throughput setting). */
     int32_t full_search;
+    /* 1 (default) = batches of launches that repeat inside one call (8
+     * rounds that start at the same ring slot, 8 proposal rounds, 8 BFS
+     * levels) are captured once per call into a HIP graph and replayed as
+     * one launch each; 0 = every kernel is launched directly.  Results do
+     * not depend on it.  Timed solves (timing != 0) launch directly. */
+    int32_t graph;
 } hwpm_options;
 
 typedef struct {
@@ -150,7 +156,9 @@ typedef struct {
     float ms_final;          /* total weight + output copy */
     float ms_total;          /* whole call, host wall clock */
     float ms_search_first;   /* Steps A-C of the first round alone */
-    float ms_reserved;
+    int32_t graph_launches;  /* batches of launches replayed from a captured graph (options.graph) */
+    int32_t probe_used;      /* the probe and tile width the rounds ran with (defaults, options */
+    int32_t tile_used;       /* or the handle's tuning table resolved) */
     /* per round (first HWPM_MAX_ROUND_STATS rounds) */
     int32_t round_candidates[HWPM_MAX_ROUND_STATS]; /* roots that kept a cycle (Step C) */
     int32_t round_applied[HWPM_MAX_ROUND_STATS];    /* cycles flipped (Step D) */
@@ -159,7 +167,7 @@ typedef struct {
 } hwpm_stats;
 
 /* Fill *opt with the defaults: max_rounds 0, check_csc 1, timing 0,
- * tile_width 0, probe 0, mcm_plain 0, full_search 0. */
+ * tile_width 0, probe 0, mcm_plain 0, full_search 0, graph 1. */
 void hwpm_default_options(hwpm_options* opt);
 
 /* Text for a status code (static storage). */
@@ -254,6 +262,41 @@ int hwpm_match(hwpm_handle h, const hwpm_csc* A, int32_t* perm_out, double* tota
 int hwpm_autotune(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
                   hwpm_options* opt, float* ms_out, void* workspace, size_t workspace_bytes);
 
+/* ---- tuning table by degree bin -------------------------------------------
+ * Launch configurations chosen per bin of average entries per column,
+ * nnz / n: bin b holds the matrices (or packed batches) with
+ * max_degree[b-1] < nnz / n <= max_degree[b]; the last bin has no upper
+ * bound.  An entry with probe 0 is untuned (the library's defaults).
+ * Batches (hwpm_improve_batch, hwpm_match_batch) whose options leave probe
+ * and tile_width at 0 take the entry of the packed batch's bin from the
+ * handle's table (hwpm_set_tune_table); the server tunes a table of its own
+ * online (hwpm_server_options.tune).  Outputs never depend on the table. */
+#define HWPM_TUNE_BINS 6
+typedef struct {
+    float max_degree[HWPM_TUNE_BINS];     /* bin bounds, increasing */
+    int32_t probe[HWPM_TUNE_BINS];        /* 0 = untuned */
+    int32_t tile_width[HWPM_TUNE_BINS];
+    float ms_per_mentry[HWPM_TUNE_BINS];  /* tuned solve time per million columns + entries */
+} hwpm_tune_table;
+
+/* Bins of at most 4, 8, 16, 32 and 64 entries per column and one above;
+ * every entry untuned. */
+void hwpm_default_tune_table(hwpm_tune_table* t);
+
+/* Bin of a matrix (or batch) with n columns and nnz entries (0 for n = 0);
+ * -1 for a NULL table. */
+int hwpm_tune_bin(const hwpm_tune_table* t, int32_t n, int64_t nnz);
+
+/* Copy *t into the handle (NULL: no table, library defaults). */
+int hwpm_set_tune_table(hwpm_handle h, const hwpm_tune_table* t);
+
+/* Tune the bin of one representative matrix: hwpm_autotune on it (from
+ * mate_in, with the handle's other defaults) and its winner written into
+ * the entry of the matrix's bin in *t.  perm_out as in hwpm_autotune.
+ * Errors as hwpm_improve. */
+int hwpm_autotune_table(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
+                        hwpm_tune_table* t, void* workspace, size_t workspace_bytes);
+
 /* ---- batches -------------------------------------------------------------
  * Many matrices solved in one call.  The batch is packed into one
  * block-diagonal matrix in the workspace and solved by the same kernels: no
@@ -315,15 +358,26 @@ int hwpm_match_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, int32_t
  * hwpm_server_destroy has returned).  The server allocates its arena
  * (arena_bytes of device memory) and one stream and handle per worker;
  * hwpm_server_destroy finishes the queued requests and frees everything.
- * hwpm_submit, hwpm_poll and hwpm_server_get_stats are thread-safe; none of
- * them may run concurrently with hwpm_server_destroy. */
+ *
+ * Threads: hwpm_submit, hwpm_poll and hwpm_server_get_stats are
+ * thread-safe.  A ticket belongs to the first hwpm_poll that waits for it or
+ * takes its result: any other call with that ticket returns HWPM_EINVAL.
+ * Once hwpm_server_destroy has begun, hwpm_poll returns HWPM_EINVAL; polls
+ * already waiting receive their results and return before destroy frees the
+ * server.  No call may start after hwpm_server_destroy has returned, and
+ * hwpm_submit and hwpm_server_get_stats may not overlap it. */
 typedef struct hwpm_server_s* hwpm_server;
 
 typedef struct {
     int32_t device;          /* HIP device ordinal */
     int32_t workers;         /* worker streams, 1..16 */
     int32_t max_batch;       /* most requests one batch admits, >= 1 */
-    int32_t reserved;
+    /* 1 (default) = tune (probe, tile_width) per degree bin online: the
+     * first batches of each bin are solved under each candidate
+     * configuration in turn (results never depend on it), and the fastest
+     * per column and entry is kept for the bin's later batches; 0 = use
+     * solve.probe / solve.tile_width as given. */
+    int32_t tune;
     size_t arena_bytes;      /* device memory the server owns, >= 1 MiB */
     hwpm_options solve;      /* options of every hwpm_match_batch call */
 } hwpm_server_options;
@@ -371,7 +425,8 @@ int hwpm_server_destroy(hwpm_server s);
 int hwpm_submit(hwpm_server s, const hwpm_csc* A, uint64_t* ticket);
 
 /* Result of a request.  wait = 0 returns HWPM_PENDING at once if it has not
- * finished; wait = 1 blocks until it has.  On completion returns the
+ * finished; wait = 1 blocks until it has (and claims the ticket: a second
+ * caller of the same ticket gets HWPM_EINVAL).  On completion returns the
  * request's status (HWPM_OK, HWPM_ESINGULAR, HWPM_EBADCSC, HWPM_ETOOBIG when
  * it cannot fit the arena even alone, or the batch's error), writes perm_host (host
  * int32[n], nullable) and *total (nullable) when HWPM_OK, fills *info
@@ -380,6 +435,9 @@ int hwpm_poll(hwpm_server s, uint64_t ticket, int32_t wait, int32_t* perm_host, 
               hwpm_request_info* info);
 
 int hwpm_server_get_stats(hwpm_server s, hwpm_server_stats* st);
+
+/* The server's online tuning table (untuned bins have probe 0). */
+int hwpm_server_get_tune_table(hwpm_server s, hwpm_tune_table* t);
 
 #ifdef __cplusplus
 }

@@ -15,6 +15,9 @@ struct hwpm_handle_s {
     int device;
     hipStream_t stream;
     int cus;
+    hipStream_t cap;      // private stream that repeated batches of launches are captured on
+    bool has_tune;        // batches resolve default launch configurations from `tune`
+    hwpm_tune_table tune;
     int32_t* host;        // pinned host buffer for counter / result readback
     // 0-7: stage events; 8 + 4*b .. 8 + 4*b + 3: the stages of the b-th
     // round of a batch of queued rounds
@@ -87,6 +90,44 @@ float elapsed(hipEvent_t a, hipEvent_t b) {
     return ms;
 }
 
+// A batch of launches captured into a HIP graph, replayed as one launch.
+struct CapturedBatch {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    CapturedBatch() = default;
+    CapturedBatch(const CapturedBatch&) = delete;
+    CapturedBatch& operator=(const CapturedBatch&) = delete;
+    ~CapturedBatch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+// Queue a batch of launches on stream s as one graph launch.  queue(stream)
+// issues the launches on the stream it is given; the first call captures them
+// on the handle's capture stream, later calls replay the same graph (the
+// caller only replays batches whose launch arguments are all the same).  The
+// batches contain kernels only: no memset or copy nodes.
+template <class F>
+int replay(hwpm_handle h, hipStream_t s, CapturedBatch& C, hwpm_stats* S, F queue) {
+    if (!C.exec) {
+        HIP_TRY(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+        const int st = queue(h->cap);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(h->cap, &g);
+        if (st != HWPM_OK || e != hipSuccess || !g) {
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipGetLastError();
+            return st != HWPM_OK ? st : HWPM_EDEVICE;
+        }
+        C.graph = g;
+        HIP_TRY(hipGraphInstantiate(&C.exec, g, nullptr, nullptr, 0));
+    }
+    HIP_TRY(hipGraphLaunch(C.exec, s));
+    ++S->graph_launches;
+    return HWPM_OK;
+}
+
 // The rounds of Section 5.3 from the perfect matching mate_in (CSC already
 // validated or trusted).  Fills the round statistics of *Sp.
 int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_in,
@@ -112,6 +153,8 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     // (a hit or a mate refresh searches its entry's position instead)
     const bool light = probe == 5 && transpose_without_positions(A.n, A.nnz);
     if (probe == 5) probe = 3;
+    S.probe_used = light ? 5 : probe;
+    S.tile_used = tile;
     const bool transposed = probe >= 2;
     const bool incremental = probe >= 3 && !opt.full_search;
     Work Wr = W;  // the round kernels' view of the workspace
@@ -187,29 +230,42 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
         if (timing) HIP_TRY(hipEventRecord(ev[7], s));
         return HWPM_OK;
     };
+    // the kernels of rounds r0 .. r0 + nb - 1, on stream st
+    auto queue_rounds = [&](hipStream_t st, int32_t r0, int32_t nb, int32_t set) -> int {
+        for (int32_t b = 0; b < nb; ++b) {
+            const int32_t r = r0 + b;
+            const int slot = r % kSlots;
+            const bool listed = incremental && r > 0;
+            hipEvent_t* e = ev + 8 + 4 * (kSlots * set + b);
+            if (tsearch) HIP_TRY(hipEventRecord(e[0], st));
+            HIP_TRY(launch_search(A, Wr, tile, kLongThreshold, slot, n_long > 0, probe, listed, incremental, st,
+                                  h->cus));
+            if (tsearch) HIP_TRY(hipEventRecord(e[1], st));
+            HIP_TRY(launch_collect(A, W, slot, st, h->cus));
+            HIP_TRY(launch_resolve(W, slot, st, h->cus));
+            if (timing) HIP_TRY(hipEventRecord(e[2], st));
+            HIP_TRY(launch_apply(A, W, slot, transposed, st, h->cus));
+            if (transposed) HIP_TRY(launch_mrk_update(A, Wr, slot, incremental, st, h->cus));
+            if (BP) HIP_TRY(launch_item_rounds(*BP, W.counters + kDone, st));
+            if (timing) HIP_TRY(hipEventRecord(e[3], st));
+            HIP_TRY(launch_round_end(W, slot, listed, n, st));
+        }
+        return HWPM_OK;
+    };
+    // Batches from the third on hold kSlots rounds that start at the same ring
+    // slot (rounds 6, 14, 22, ...), so their launches are all the same: with
+    // opt.graph they replay one graph captured at the first of them.
+    CapturedBatch rounds_graph;
     for (;;) {
         int32_t nb = batch;
         if (opt.max_rounds > 0 && opt.max_rounds - round < nb) nb = opt.max_rounds - round;
         if (nb <= 0) break;  // the round cap
         const int32_t set = batches & 1;
-        for (int32_t b = 0; b < nb; ++b) {
-            const int32_t r = round + b;
-            const int slot = r % kSlots;
-            const bool listed = incremental && r > 0;
-            hipEvent_t* e = ev + 8 + 4 * (kSlots * set + b);
-            if (tsearch) HIP_TRY(hipEventRecord(e[0], s));
-            HIP_TRY(launch_search(A, Wr, tile, kLongThreshold, slot, n_long > 0, probe, listed, incremental, s,
-                                  h->cus));
-            if (tsearch) HIP_TRY(hipEventRecord(e[1], s));
-            HIP_TRY(launch_collect(A, W, slot, s, h->cus));
-            HIP_TRY(launch_resolve(W, slot, s, h->cus));
-            if (timing) HIP_TRY(hipEventRecord(e[2], s));
-            HIP_TRY(launch_apply(A, W, slot, transposed, s, h->cus));
-            if (transposed) HIP_TRY(launch_mrk_update(A, Wr, slot, incremental, s, h->cus));
-            if (BP) HIP_TRY(launch_item_rounds(*BP, W.counters + kDone, s));
-            if (timing) HIP_TRY(hipEventRecord(e[3], s));
-            HIP_TRY(launch_round_end(W, slot, r, listed, n, s));
-        }
+        const bool replayable = opt.graph && !tsearch && nb == kSlots && round % kSlots == kSlots - 2;
+        const int qs = replayable
+                           ? replay(h, s, rounds_graph, &S, [&](hipStream_t c) { return queue_rounds(c, round, nb, set); })
+                           : queue_rounds(s, round, nb, set);
+        if (qs != HWPM_OK) return qs;
         round += nb;
         ++batches;
         // single solves queue the output stage behind every batch, gated on
@@ -289,6 +345,7 @@ int check_options(const hwpm_options& opt) {
     if (opt.mcm_plain != 0 && opt.mcm_plain != 1) return HWPM_EINVAL;
     if (opt.full_search != 0 && opt.full_search != 1) return HWPM_EINVAL;
     if (opt.timing < 0 || opt.timing > 2) return HWPM_EINVAL;
+    if (opt.graph != 0 && opt.graph != 1) return HWPM_EINVAL;
     return HWPM_OK;
 }
 
@@ -296,7 +353,7 @@ int check_options(const hwpm_options& opt) {
 // no augmenting path is found.  Leaves a perfect matching in M.mc, or returns
 // HWPM_ESINGULAR.
 int run_initial_matching(hwpm_handle h, const Csc& A, const Work& W, const Mcm& M, int heavy,
-                         bool timing, hwpm_stats* S) {
+                         bool timing, bool graph, hwpm_stats* S) {
     hipStream_t s = h->stream;
     hipEvent_t* ev = h->ev;
     int32_t* host = h->host;
@@ -309,9 +366,17 @@ int run_initial_matching(hwpm_handle h, const Csc& A, const Work& W, const Mcm& 
     // greedy rounds, queued in batches of 1, 2, 4, 8, 8, ... (the round that
     // finds no proposal ends the loop on the device)
     HIP_TRY(hipMemsetAsync(M.counters, 0, kMcmWords * sizeof(int32_t), s));
+    // batches of 8 rounds (and of 8 BFS levels, which start at an odd level)
+    // are all the same: with graph they replay one captured graph
+    CapturedBatch greedy_graph, level_graph;
     for (int32_t batch = 1;; batch = batch < 8 ? 2 * batch : 8) {
-        for (int32_t b = 0; b < batch; ++b)
-            HIP_TRY(launch_greedy_round(A, M, W, heavy, kLongThreshold, has_long, s, h->cus));
+        auto queue = [&](hipStream_t st) -> int {
+            for (int32_t b = 0; b < batch; ++b)
+                HIP_TRY(launch_greedy_round(A, M, W, heavy, kLongThreshold, has_long, st, h->cus));
+            return HWPM_OK;
+        };
+        const int qs = (graph && batch == 8) ? replay(h, s, greedy_graph, S, queue) : queue(s);
+        if (qs != HWPM_OK) return qs;
         HIP_TRY(hipMemcpyAsync(host, M.counters + kMcmDone, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         if (host[0]) break;
@@ -340,8 +405,14 @@ int run_initial_matching(hwpm_handle h, const Csc& A, const Work& W, const Mcm& 
         // levels, queued in batches of 1, 2, 4, 8, 8, ...: a level with an
         // empty frontier does nothing, so the phase's levels end on the device
         for (int32_t level = 0, batch = 1;; batch = batch < 8 ? 2 * batch : 8) {
-            for (int32_t b = 0; b < batch; ++b, ++level)
-                HIP_TRY(launch_bfs_level(A, M, level, heavy, s, h->cus));
+            auto queue = [&](hipStream_t st) -> int {
+                for (int32_t b = 0; b < batch; ++b)
+                    HIP_TRY(launch_bfs_level(A, M, level + b, heavy, st, h->cus));
+                return HWPM_OK;
+            };
+            const int qs = (graph && batch == 8 && (level & 1)) ? replay(h, s, level_graph, S, queue) : queue(s);
+            if (qs != HWPM_OK) return qs;
+            level += batch;
             const int nw = (level & 1) ? kMcmNext : kMcmFrontier;  // next level's frontier
             HIP_TRY(hipMemcpyAsync(host, M.counters + nw, sizeof(int32_t), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
@@ -536,6 +607,7 @@ void hwpm_default_options(hwpm_options* opt) {
     opt->probe = 0;
     opt->mcm_plain = 0;
     opt->full_search = 0;
+    opt->graph = 1;
 }
 
 const char* hwpm_strerror(int status) {
@@ -565,12 +637,16 @@ int hwpm_create(hwpm_handle* out, int device, void* stream) {
     h->device = device;
     h->stream = (hipStream_t)stream;
     h->host = nullptr;
+    h->cap = nullptr;
+    h->has_tune = false;
+    hwpm_default_tune_table(&h->tune);
     if (hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         h->cus <= 0)
         h->cus = 256;
     constexpr int kEvents = (int)(sizeof(h->ev) / sizeof(h->ev[0]));
     int ne = 0;
-    bool ok = hipHostMalloc((void**)&h->host, kHostBytes, hipHostMallocDefault) == hipSuccess;
+    bool ok = hipHostMalloc((void**)&h->host, kHostBytes, hipHostMallocDefault) == hipSuccess &&
+              hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) == hipSuccess;
     while (ok && ne < kEvents) {
         // timing only (host data is always read after a stream synchronize):
         // no system-scope cache flush at each record
@@ -580,6 +656,7 @@ int hwpm_create(hwpm_handle* out, int device, void* stream) {
     if (!ok) {
         for (int e = 0; e < ne; ++e) (void)hipEventDestroy(h->ev[e]);
         if (h->host) (void)hipHostFree(h->host);
+        if (h->cap) (void)hipStreamDestroy(h->cap);
         delete h;
         return HWPM_EDEVICE;
     }
@@ -593,6 +670,7 @@ int hwpm_destroy(hwpm_handle h) {
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
     (void)hipHostFree(h->host);
+    (void)hipStreamDestroy(h->cap);
     delete h;
     return HWPM_OK;
 }
@@ -698,7 +776,7 @@ int hwpm_match(hwpm_handle h, const hwpm_csc* Ain, int32_t* perm_out, double* to
     }
     // a perfect matching takes n distinct entries
     if (A.nnz < (int64_t)n) return HWPM_ESINGULAR;
-    st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, timing, &S);
+    st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, timing, opt.graph != 0, &S);
     if (st != HWPM_OK) return st;
     double total = 0.0;
     st = run_improve(h, A, W, M.mc, perm_out, &total, opt, &S);
@@ -733,6 +811,15 @@ static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const i
     HostPlan HP;
     st = build_plan(count, mats, match ? nullptr : mate_in, perm_out, &HP);
     if (st != HWPM_OK) return st;
+    // default launch configuration: the handle's tuning table, by the packed
+    // batch's degree bin
+    if (h->has_tune && opt.probe == 0 && opt.tile_width == 0) {
+        const int b = hwpm_tune_bin(&h->tune, (int32_t)(HP.n_tot < INT32_MAX ? HP.n_tot : INT32_MAX - 1), HP.nnz_tot);
+        if (b >= 0 && h->tune.probe[b] != 0) {
+            opt.probe = h->tune.probe[b];
+            opt.tile_width = h->tune.tile_width[b];
+        }
+    }
     hwpm_stats S;
     memset(&S, 0, sizeof(S));
     if (HP.n_tot == 0) {
@@ -775,7 +862,7 @@ static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const i
     if (h->host[0] & 4) return HWPM_EBADMATCH;
     const int32_t* start = P.mate;
     if (match) {
-        st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, opt.timing == 1, &S);
+        st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, opt.timing == 1, opt.graph != 0, &S);
         if (st == HWPM_ESINGULAR) {
             // some blocks have no perfect matching: solve the others one by one
             std::vector<int32_t> unm(count);
@@ -857,6 +944,58 @@ int hwpm_autotune(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int3
         for (int c = 0; c < HWPM_TUNE_CANDIDATES; ++c) ms_out[c] = best_ms[c];
     opt->probe = kCand[win][0];
     opt->tile_width = kCand[win][1];
+    return HWPM_OK;
+}
+
+void hwpm_default_tune_table(hwpm_tune_table* t) {
+    if (!t) return;
+    memset(t, 0, sizeof(*t));
+    static const float kBounds[HWPM_TUNE_BINS] = {4.f, 8.f, 16.f, 32.f, 64.f, 3.0e38f};
+    for (int b = 0; b < HWPM_TUNE_BINS; ++b) t->max_degree[b] = kBounds[b];
+}
+
+int hwpm_tune_bin(const hwpm_tune_table* t, int32_t n, int64_t nnz) {
+    if (!t) return -1;
+    if (n <= 0) return 0;
+    const double d = (double)nnz / (double)n;
+    for (int b = 0; b + 1 < HWPM_TUNE_BINS; ++b)
+        if (d <= (double)t->max_degree[b]) return b;
+    return HWPM_TUNE_BINS - 1;
+}
+
+int hwpm_set_tune_table(hwpm_handle h, const hwpm_tune_table* t) {
+    if (!h) return HWPM_EINVAL;
+    if (!t) {
+        h->has_tune = false;
+        return HWPM_OK;
+    }
+    for (int b = 0; b < HWPM_TUNE_BINS; ++b) {
+        if (b > 0 && !(t->max_degree[b] > t->max_degree[b - 1])) return HWPM_EINVAL;
+        hwpm_options o;
+        hwpm_default_options(&o);
+        o.probe = t->probe[b];
+        o.tile_width = t->tile_width[b];
+        if (t->probe[b] != 0 && check_options(o) != HWPM_OK) return HWPM_EINVAL;
+    }
+    h->tune = *t;
+    h->has_tune = true;
+    return HWPM_OK;
+}
+
+int hwpm_autotune_table(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
+                        hwpm_tune_table* t, void* workspace, size_t workspace_bytes) {
+    if (!h || !A || !t) return HWPM_EINVAL;
+    hwpm_options o;
+    hwpm_default_options(&o);
+    float ms[HWPM_TUNE_CANDIDATES];
+    const int st = hwpm_autotune(h, A, mate_in, perm_out, &o, ms, workspace, workspace_bytes);
+    if (st != HWPM_OK) return st;
+    const int b = hwpm_tune_bin(t, A->n, A->nnz);
+    float best = ms[0];
+    for (int c = 1; c < HWPM_TUNE_CANDIDATES; ++c) best = ms[c] < best ? ms[c] : best;
+    t->probe[b] = o.probe;
+    t->tile_width[b] = o.tile_width;
+    t->ms_per_mentry[b] = best / (float)(((double)A->n + (double)A->nnz) * 1e-6 + 1e-12);
     return HWPM_OK;
 }
 

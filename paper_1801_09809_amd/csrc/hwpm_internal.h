@@ -222,7 +222,7 @@ hipError_t launch_long_chunks(const Work& W, const Csc& A, hipStream_t s);
 hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t long_threshold,
                          int slot, bool has_long, int probe, bool listed, bool incremental, hipStream_t s,
                          int cus);
-hipError_t launch_round_end(const Work& W, int slot, int round, bool listed, int32_t n, hipStream_t s);
+hipError_t launch_round_end(const Work& W, int slot, bool listed, int32_t n, hipStream_t s);
 hipError_t launch_collect(const Csc& A, const Work& W, int slot, hipStream_t s, int cus);
 hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
                             bool positions, hipStream_t s, int cus);

@@ -995,8 +995,11 @@ __global__ __launch_bounds__(256) void k_mrk_update_heavy(Csc A, Work W, int slo
 // the device flag that turns every later round kernel into a no-op (the
 // loop's exit test of Algorithm 2, taken on the device so that the host can
 // queue several rounds between two looks at the flag).
-__global__ void k_round_end(Work W, int slot, int round, int listed, int32_t n) {
+// The round's index is read on the device (rounds run so far), so that the
+// same launches serve every batch of rounds with the same ring slots.
+__global__ void k_round_end(Work W, int slot, int listed, int32_t n) {
     if (round_over(W)) return;
+    const int32_t round = W.counters[kRoundsRun];
     const int32_t cand = W.counters[slot_word(slot, kCand)];
     const int32_t applied = W.counters[slot_word(slot, kApplied)];
     if (round < kMaxRoundStats) {
@@ -1009,8 +1012,8 @@ __global__ void k_round_end(Work W, int slot, int round, int listed, int32_t n) 
     if (applied == 0) W.counters[kDone] = cand > 0 ? 2 : 1;
 }
 
-hipError_t launch_round_end(const Work& W, int slot, int round, bool listed, int32_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, W, slot, round, listed ? 1 : 0, n);
+hipError_t launch_round_end(const Work& W, int slot, bool listed, int32_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_round_end, dim3(1), dim3(1), 0, s, W, slot, listed ? 1 : 0, n);
     return hipGetLastError();
 }
 

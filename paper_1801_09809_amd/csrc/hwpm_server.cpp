@@ -46,6 +46,7 @@ struct Request {
     size_t input_bytes = 0;  // arena bytes for its arrays and its result
     Clock::time_point t_submit, t_admit, t_done;
     bool done = false;
+    bool claimed = false;  // a waiting hwpm_poll owns the ticket
     int status = HWPM_PENDING;
     std::vector<int32_t> perm;
     double total = 0.0;
@@ -100,6 +101,12 @@ class Arena {
     size_t in_use_ = 0, peak_ = 0;
 };
 
+// Online tuning: the (probe, tile width) candidates each degree bin tries,
+// and how many batches each candidate solves before the bin is decided.
+constexpr int kTuneCand = 6;
+constexpr int32_t kTuneConfigs[kTuneCand][2] = {{5, 4}, {5, 8}, {3, 4}, {3, 8}, {4, 4}, {4, 8}};
+constexpr int kTuneTrials = 2;
+
 }  // namespace
 
 struct hwpm_server_s {
@@ -111,13 +118,21 @@ struct hwpm_server_s {
     std::mutex mu;
     std::condition_variable cv_work;  // a new request, freed arena space or stop
     std::condition_variable cv_done;  // a result is ready
+    std::condition_variable cv_idle;  // the last waiting hwpm_poll left (during destroy)
     std::deque<Request*> pending;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
     uint64_t next_ticket = 1;
     bool stop = false;
+    bool closing = false;     // hwpm_server_destroy has begun: no new polls
+    int32_t active_polls = 0; // hwpm_poll calls waiting for a result
     int32_t running = 0;
     hwpm_server_stats stats{};
     std::vector<std::thread> threads;
+    // online tuning table and its trials (under mu)
+    hwpm_tune_table table{};
+    int32_t trials_started[HWPM_TUNE_BINS] = {};
+    int32_t trials_done[HWPM_TUNE_BINS] = {};
+    float trial_ms[HWPM_TUNE_BINS][kTuneCand] = {};
 };
 
 namespace {
@@ -171,7 +186,9 @@ std::vector<Request*> take_batch(hwpm_server_s* S, size_t* off, size_t* bytes) {
 }
 
 // Copy the batch into its arena region, solve it and copy the results back.
-int solve_batch(hwpm_server_s* S, int index, std::vector<Request*>& batch, char* base, size_t bytes) {
+// solve_ms (out): host time of the batch solve itself (after the copies in).
+int solve_batch(hwpm_server_s* S, int index, std::vector<Request*>& batch, char* base, size_t bytes,
+                const hwpm_options& solve, double* solve_ms) {
     hipStream_t stream = S->streams[index];
     size_t at = 0;
     std::vector<hwpm_csc> mats(batch.size());
@@ -201,14 +218,17 @@ int solve_batch(hwpm_server_s* S, int index, std::vector<Request*>& batch, char*
     std::vector<double> totals(batch.size());
     std::vector<hwpm_item_stats> items(batch.size());
     hwpm_handle h = S->handles[index];
-    int st = hwpm_match_batch(h, (int32_t)batch.size(), mats.data(), perms.data(), totals.data(), &S->opt.solve,
+    if (hipStreamSynchronize(stream) != hipSuccess) return HWPM_EDEVICE;  // inputs in place
+    const auto t0 = Clock::now();
+    int st = hwpm_match_batch(h, (int32_t)batch.size(), mats.data(), perms.data(), totals.data(), &solve,
                               items.data(), nullptr, base + at, bytes - at);
+    *solve_ms = ms_between(t0, Clock::now());
     if (st == HWPM_EBADCSC && batch.size() > 1) {
         // a malformed member fails the whole batch: solve the members alone so
         // that only the malformed ones report it
         for (size_t i = 0; i < batch.size(); ++i) {
             hwpm_stats one;
-            const int si = hwpm_match(h, &mats[i], perms[i], &totals[i], &S->opt.solve, &one, base + at, bytes - at);
+            const int si = hwpm_match(h, &mats[i], perms[i], &totals[i], &solve, &one, base + at, bytes - at);
             memset(&items[i], 0, sizeof(items[i]));
             items[i].status = si;
             if (si == HWPM_OK) {
@@ -247,6 +267,9 @@ void worker(hwpm_server_s* S, int index) {
     for (;;) {
         std::vector<Request*> batch;
         size_t off = 0, bytes = 0;
+        hwpm_options solve;
+        int cand = -1, bin = -1;
+        double work = 0.0;
         {
             std::unique_lock<std::mutex> lk(S->mu);
             for (;;) {
@@ -257,17 +280,57 @@ void worker(hwpm_server_s* S, int index) {
             if (batch.empty()) return;
             const auto now = Clock::now();
             for (Request* r : batch) r->t_admit = now;
+            // launch configuration: the bin's tuned entry, or the bin's next
+            // candidate while the bin is still being tuned
+            solve = S->opt.solve;
+            cand = -1;
+            int64_t n_tot = 0, nnz_tot = 0;
+            for (Request* r : batch) {
+                n_tot += r->n;
+                nnz_tot += r->nnz;
+            }
+            work = (double)n_tot + (double)nnz_tot;
+            bin = hwpm_tune_bin(&S->table, (int32_t)std::min<int64_t>(n_tot, INT32_MAX - 1), nnz_tot);
+            if (S->opt.tune && bin >= 0) {
+                if (S->table.probe[bin] != 0) {
+                    solve.probe = S->table.probe[bin];
+                    solve.tile_width = S->table.tile_width[bin];
+                } else {
+                    cand = S->trials_started[bin]++ % kTuneCand;
+                    solve.probe = kTuneConfigs[cand][0];
+                    solve.tile_width = kTuneConfigs[cand][1];
+                }
+            }
             ++S->running;
             ++S->stats.batches;
             S->stats.max_batch_seen = std::max<int64_t>(S->stats.max_batch_seen, (int64_t)batch.size());
             S->stats.max_running = std::max<int64_t>(S->stats.max_running, S->running);
         }
-        const int st = solve_batch(S, index, batch, S->arena_base + off, bytes);
+        double solve_ms = 0.0;
+        const int st = solve_batch(S, index, batch, S->arena_base + off, bytes, solve, &solve_ms);
         if (st != HWPM_OK) (void)hipStreamSynchronize(S->streams[index]);  // nothing may still use the region
         {
             std::lock_guard<std::mutex> lk(S->mu);
             S->arena->release(off, bytes);
             --S->running;
+            if (cand >= 0 && st == HWPM_OK && S->table.probe[bin] == 0) {
+                // a trial: keep the candidate's best time per million columns
+                // and entries; once every candidate has had its trials the bin
+                // takes the fastest
+                const float ms = (float)(solve_ms / (work * 1e-6 + 1e-12));
+                float& best = S->trial_ms[bin][cand];
+                if (best == 0.f || ms < best) best = ms;
+                if (++S->trials_done[bin] >= kTuneCand * kTuneTrials) {
+                    int win = 0;
+                    for (int c = 1; c < kTuneCand; ++c)
+                        if (S->trial_ms[bin][c] > 0.f &&
+                            (S->trial_ms[bin][win] == 0.f || S->trial_ms[bin][c] < S->trial_ms[bin][win]))
+                            win = c;
+                    S->table.probe[bin] = kTuneConfigs[win][0];
+                    S->table.tile_width[bin] = kTuneConfigs[win][1];
+                    S->table.ms_per_mentry[bin] = S->trial_ms[bin][win];
+                }
+            }
             const auto now = Clock::now();
             for (Request* r : batch) {
                 if (st != HWPM_OK) r->status = st;
@@ -302,6 +365,7 @@ void hwpm_server_default_options(hwpm_server_options* opt) {
     opt->device = 0;
     opt->workers = 2;
     opt->max_batch = 64;
+    opt->tune = 1;
     opt->arena_bytes = (size_t)8 << 30;
     hwpm_default_options(&opt->solve);  // check_csc = 1: requests are validated on the device
 }
@@ -311,7 +375,8 @@ int hwpm_server_create(hwpm_server* out, const hwpm_server_options* opt_in) {
     hwpm_server_options opt;
     hwpm_server_default_options(&opt);
     if (opt_in) opt = *opt_in;
-    if (opt.workers < 1 || opt.workers > 16 || opt.max_batch < 1 || opt.arena_bytes < ((size_t)1 << 20))
+    if (opt.workers < 1 || opt.workers > 16 || opt.max_batch < 1 || opt.arena_bytes < ((size_t)1 << 20) ||
+        (opt.tune != 0 && opt.tune != 1))
         return HWPM_EINVAL;
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || opt.device < 0 || opt.device >= count) return HWPM_EDEVICE;
@@ -320,6 +385,7 @@ int hwpm_server_create(hwpm_server* out, const hwpm_server_options* opt_in) {
     if (hipSetDevice(opt.device) != hipSuccess) return HWPM_EDEVICE;
     auto* S = new hwpm_server_s();
     S->opt = opt;
+    hwpm_default_tune_table(&S->table);
     int st = HWPM_OK;
     void* p = nullptr;
     if (hipMalloc(&p, opt.arena_bytes) != hipSuccess) {
@@ -355,9 +421,16 @@ int hwpm_server_destroy(hwpm_server s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
+        s->closing = true;
     }
     s->cv_work.notify_all();
-    for (auto& t : s->threads) t.join();
+    for (auto& t : s->threads) t.join();  // every queued request completes
+    {
+        // polls already waiting get their results and leave before the
+        // server's memory goes
+        std::unique_lock<std::mutex> lk(s->mu);
+        s->cv_idle.wait(lk, [s] { return s->active_polls == 0; });
+    }
     int prev = -1;
     if (hipGetDevice(&prev) != hipSuccess) prev = -1;
     (void)hipSetDevice(s->opt.device);
@@ -398,12 +471,19 @@ int hwpm_poll(hwpm_server s, uint64_t ticket, int32_t wait, int32_t* perm_host, 
               hwpm_request_info* info) {
     if (!s) return HWPM_EINVAL;
     std::unique_lock<std::mutex> lk(s->mu);
+    if (s->closing) return HWPM_EINVAL;
     auto it = s->requests.find(ticket);
     if (it == s->requests.end()) return HWPM_EINVAL;
     Request* r = it->second.get();
+    if (r->claimed) return HWPM_EINVAL;  // another caller is waiting for this ticket
     if (!r->done) {
         if (!wait) return HWPM_PENDING;
+        // claim the ticket, so that no other caller reads or frees the
+        // request while this one waits (workers complete every request)
+        r->claimed = true;
+        ++s->active_polls;
         s->cv_done.wait(lk, [r] { return r->done; });
+        if (--s->active_polls == 0 && s->closing) s->cv_idle.notify_all();
     }
     const int status = r->status;
     if (status == HWPM_OK) {
@@ -420,6 +500,13 @@ int hwpm_poll(hwpm_server s, uint64_t ticket, int32_t wait, int32_t* perm_host, 
     }
     s->requests.erase(it);
     return status;
+}
+
+int hwpm_server_get_tune_table(hwpm_server s, hwpm_tune_table* t) {
+    if (!s || !t) return HWPM_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *t = s->table;
+    return HWPM_OK;
 }
 
 int hwpm_server_get_stats(hwpm_server s, hwpm_server_stats* st) {

@@ -36,7 +36,8 @@ EXPORTED = (
     "hwpm_workspace_bytes", "hwpm_check_csc", "hwpm_improve", "hwpm_match",
     "hwpm_autotune", "hwpm_batch_workspace_bytes", "hwpm_improve_batch", "hwpm_match_batch",
     "hwpm_server_default_options", "hwpm_server_create", "hwpm_server_destroy",
-    "hwpm_submit", "hwpm_poll", "hwpm_server_get_stats",
+    "hwpm_submit", "hwpm_poll", "hwpm_server_get_stats", "hwpm_server_get_tune_table",
+    "hwpm_default_tune_table", "hwpm_tune_bin", "hwpm_set_tune_table", "hwpm_autotune_table",
 )
 
 
@@ -65,6 +66,7 @@ class hwpm_options(ctypes.Structure):
         ("probe", ctypes.c_int32),
         ("mcm_plain", ctypes.c_int32),
         ("full_search", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
     ]
 
 
@@ -92,7 +94,9 @@ class hwpm_stats(ctypes.Structure):
         ("ms_final", ctypes.c_float),
         ("ms_total", ctypes.c_float),
         ("ms_search_first", ctypes.c_float),
-        ("ms_reserved", ctypes.c_float),
+        ("graph_launches", ctypes.c_int32),
+        ("probe_used", ctypes.c_int32),
+        ("tile_used", ctypes.c_int32),
         ("round_candidates", ctypes.c_int32 * MAX_ROUND_STATS),
         ("round_applied", ctypes.c_int32 * MAX_ROUND_STATS),
         ("round_ms_search", ctypes.c_float * MAX_ROUND_STATS),
@@ -102,7 +106,7 @@ class hwpm_stats(ctypes.Structure):
     def as_dict(self) -> dict:
         nr = min(self.rounds, MAX_ROUND_STATS)
         d = {name: getattr(self, name) for name, _ in self._fields_
-             if not name.startswith("round_") and name != "ms_reserved"}
+             if not name.startswith("round_")}
         d["round_candidates"] = list(self.round_candidates[:nr])
         d["round_applied"] = list(self.round_applied[:nr])
         d["round_ms_search"] = list(self.round_ms_search[:nr])
@@ -125,12 +129,29 @@ class hwpm_item_stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+TUNE_BINS = 6  # HWPM_TUNE_BINS
+
+
+class hwpm_tune_table(ctypes.Structure):
+    _fields_ = [
+        ("max_degree", ctypes.c_float * TUNE_BINS),
+        ("probe", ctypes.c_int32 * TUNE_BINS),
+        ("tile_width", ctypes.c_int32 * TUNE_BINS),
+        ("ms_per_mentry", ctypes.c_float * TUNE_BINS),
+    ]
+
+    def as_list(self) -> list:
+        return [{"max_degree": float(self.max_degree[b]), "probe": int(self.probe[b]),
+                 "tile_width": int(self.tile_width[b]), "ms_per_mentry": float(self.ms_per_mentry[b])}
+                for b in range(TUNE_BINS)]
+
+
 class hwpm_server_options(ctypes.Structure):
     _fields_ = [
         ("device", ctypes.c_int32),
         ("workers", ctypes.c_int32),
         ("max_batch", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("tune", ctypes.c_int32),
         ("arena_bytes", ctypes.c_size_t),
         ("solve", hwpm_options),
     ]
@@ -217,6 +238,17 @@ def load_library(path: str = LIB_PATH):
                                   ctypes.POINTER(hwpm_request_info)]
         lib.hwpm_server_get_stats.restype = ctypes.c_int
         lib.hwpm_server_get_stats.argtypes = [vp, ctypes.POINTER(hwpm_server_stats)]
+        lib.hwpm_server_get_tune_table.restype = ctypes.c_int
+        lib.hwpm_server_get_tune_table.argtypes = [vp, ctypes.POINTER(hwpm_tune_table)]
+        lib.hwpm_default_tune_table.restype = None
+        lib.hwpm_default_tune_table.argtypes = [ctypes.POINTER(hwpm_tune_table)]
+        lib.hwpm_tune_bin.restype = ctypes.c_int
+        lib.hwpm_tune_bin.argtypes = [ctypes.POINTER(hwpm_tune_table), i32, i64]
+        lib.hwpm_set_tune_table.restype = ctypes.c_int
+        lib.hwpm_set_tune_table.argtypes = [vp, ctypes.POINTER(hwpm_tune_table)]
+        lib.hwpm_autotune_table.restype = ctypes.c_int
+        lib.hwpm_autotune_table.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, vp, ctypes.POINTER(hwpm_tune_table),
+                                            vp, ctypes.c_size_t]
         _lib = lib
     return _lib
 
@@ -400,6 +432,38 @@ def hwpm_poll(server: int, ticket: int, wait: bool, perm_ptr: int | None):
     return st, total.value, info
 
 
+def hwpm_default_tune_table() -> hwpm_tune_table:
+    t = hwpm_tune_table()
+    load_library().hwpm_default_tune_table(ctypes.byref(t))
+    return t
+
+
+def hwpm_tune_bin(table: hwpm_tune_table, n: int, nnz: int) -> int:
+    return load_library().hwpm_tune_bin(ctypes.byref(table), int(n), int(nnz))
+
+
+def hwpm_set_tune_table(handle: int, table: hwpm_tune_table | None) -> int:
+    return load_library().hwpm_set_tune_table(ctypes.c_void_p(handle),
+                                              ctypes.byref(table) if table is not None else None)
+
+
+def hwpm_autotune_table(handle: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: int, weight_ptr: int,
+                        mate_in_ptr: int, perm_out_ptr: int, table: hwpm_tune_table, ws_ptr: int,
+                        ws_bytes: int) -> int:
+    A = _csc(n, nnz, col_ptr_ptr, row_idx_ptr, weight_ptr)
+    return load_library().hwpm_autotune_table(ctypes.c_void_p(handle), ctypes.byref(A), ctypes.c_void_p(mate_in_ptr),
+                                              ctypes.c_void_p(perm_out_ptr), ctypes.byref(table),
+                                              ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes))
+
+
+def hwpm_server_get_tune_table(server: int) -> hwpm_tune_table:
+    t = hwpm_tune_table()
+    st = load_library().hwpm_server_get_tune_table(ctypes.c_void_p(server), ctypes.byref(t))
+    if st != HWPM_OK:
+        raise HwpmError(st, "hwpm_server_get_tune_table")
+    return t
+
+
 def hwpm_server_get_stats(server: int) -> hwpm_server_stats:
     s = hwpm_server_stats()
     st = load_library().hwpm_server_get_stats(ctypes.c_void_p(server), ctypes.byref(s))
@@ -478,7 +542,7 @@ class Solver:
 
     @staticmethod
     def options(max_rounds=0, check_csc=True, timing=False, tile_width=0, probe=0,
-                mcm_plain=False, full_search=False) -> hwpm_options:
+                mcm_plain=False, full_search=False, graph=True) -> hwpm_options:
         opt = hwpm_default_options()
         opt.max_rounds = int(max_rounds)
         opt.check_csc = int(bool(check_csc))
@@ -487,6 +551,7 @@ class Solver:
         opt.probe = int(probe)
         opt.mcm_plain = int(bool(mcm_plain))
         opt.full_search = int(bool(full_search))
+        opt.graph = int(bool(graph))
         return opt
 
     def match(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
@@ -538,6 +603,32 @@ class Solver:
     def match_batch(self, mats, perms=None, **kw):
         return self._batch(mats, None, perms, True, **kw)
 
+    def set_tune_table(self, table: hwpm_tune_table | None):
+        """Batches with default launch options take their configuration from
+        this table by degree bin (None: library defaults)."""
+        st = hwpm_set_tune_table(self.handle, table)
+        if st != HWPM_OK:
+            raise HwpmError(st, "hwpm_set_tune_table")
+
+    def autotune_table(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
+                       mate_in: torch.Tensor, table: hwpm_tune_table | None = None) -> hwpm_tune_table:
+        """Tune the degree bin of this matrix; returns the table (a new default
+        one when none is given) with that bin's entry filled."""
+        n = col_ptr.numel() - 1
+        nnz = row_idx.numel()
+        self._check(col_ptr, torch.int64, "col_ptr")
+        self._check(row_idx, torch.int32, "row_idx")
+        self._check(w, torch.float64, "w", nnz)
+        self._check(mate_in, torch.int32, "mate_in", n)
+        table = table if table is not None else hwpm_default_tune_table()
+        perm = torch.empty(n, dtype=torch.int32, device=self.device)
+        ws = self._workspace(n, nnz)
+        st = hwpm_autotune_table(self.handle, n, nnz, col_ptr.data_ptr(), row_idx.data_ptr(), w.data_ptr(),
+                                 mate_in.data_ptr(), perm.data_ptr(), table, ws.data_ptr(), ws.numel())
+        if st != HWPM_OK:
+            raise HwpmError(st, "hwpm_autotune_table")
+        return table
+
     def autotune(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
                  mate_in: torch.Tensor, perm_out: torch.Tensor | None = None, **kw):
         """Returns (probe, tile_width, {(probe, tile): best ms}, perm_out)."""
@@ -560,7 +651,7 @@ class Solver:
     def improve(self, col_ptr: torch.Tensor, row_idx: torch.Tensor, w: torch.Tensor,
                 mate_in: torch.Tensor, perm_out: torch.Tensor | None = None, max_rounds: int = 0,
                 check_csc: bool = True, timing: int = 0, tile_width: int = 0,
-                probe: int = 0, full_search: bool = False) -> ImproveResult:
+                probe: int = 0, full_search: bool = False, graph: bool = True) -> ImproveResult:
         n = col_ptr.numel() - 1
         nnz = row_idx.numel()
         self._check(col_ptr, torch.int64, "col_ptr")
@@ -571,7 +662,7 @@ class Solver:
             perm_out = torch.empty(n, dtype=torch.int32, device=self.device)
         self._check(perm_out, torch.int32, "perm_out", n)
         ws = self._workspace(n, nnz)
-        opt = self.options(max_rounds, check_csc, timing, tile_width, probe, False, full_search)
+        opt = self.options(max_rounds, check_csc, timing, tile_width, probe, False, full_search, graph)
         st, total, stats = hwpm_improve(self.handle, n, nnz, col_ptr.data_ptr(), row_idx.data_ptr(),
                                         w.data_ptr(), mate_in.data_ptr(), perm_out.data_ptr(),
                                         ws.data_ptr(), ws.numel(), opt)
@@ -585,7 +676,7 @@ class Server:
     arrays of a request are kept alive here until its result is polled."""
 
     def __init__(self, device: int = 0, workers: int = 2, max_batch: int = 64,
-                 arena_bytes: int = 8 << 30, **solve_kw):
+                 arena_bytes: int = 8 << 30, tune: bool = True, **solve_kw):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HWPM library runs on the device only")
         opt = hwpm_server_default_options()
@@ -593,6 +684,7 @@ class Server:
         opt.workers = int(workers)
         opt.max_batch = int(max_batch)
         opt.arena_bytes = int(arena_bytes)
+        opt.tune = int(bool(tune))
         if solve_kw:
             opt.solve = Solver.options(**solve_kw)
         self.server = hwpm_server_create(opt)
@@ -646,3 +738,8 @@ class Server:
 
     def stats(self) -> dict:
         return hwpm_server_get_stats(self.server).as_dict()
+
+    def tune_table(self) -> list:
+        """The online tuning table: per degree bin its bound and the tuned
+        (probe, tile_width), probe 0 while untuned."""
+        return hwpm_server_get_tune_table(self.server).as_list()

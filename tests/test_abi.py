@@ -44,15 +44,15 @@ def test_status_codes_match_header():
 def test_struct_layouts():
     # the ctypes mirrors must match the C layout (offsets of the last fields)
     assert ctypes.sizeof(hwpm.hwpm_csc) == 40
-    assert ctypes.sizeof(hwpm.hwpm_options) == 28
+    assert ctypes.sizeof(hwpm.hwpm_options) == 32
     s = hwpm.hwpm_stats
     assert s.init_weight.offset == 40 and s.ms_check.offset == 56
-    assert s.round_candidates.offset == 104
-    assert ctypes.sizeof(s) == 104 + 4 * 4 * hwpm.MAX_ROUND_STATS
+    assert s.round_candidates.offset == 112
+    assert ctypes.sizeof(s) == 112 + 4 * 4 * hwpm.MAX_ROUND_STATS
 
 
 _STRUCTS = ("hwpm_csc", "hwpm_options", "hwpm_stats", "hwpm_item_stats", "hwpm_server_options",
-            "hwpm_request_info", "hwpm_server_stats")
+            "hwpm_request_info", "hwpm_server_stats", "hwpm_tune_table")
 
 
 def test_struct_layouts_match_the_c_compiler(tmp_path):
@@ -153,3 +153,15 @@ def test_solver_refuses_without_gpu():
         pytest.skip("GPU present")
     with pytest.raises(RuntimeError):
         hwpm.Solver(0)
+
+
+def test_tune_table_bins():
+    """Degree bins of the tuning table (host code only): bounds 4, 8, 16, 32,
+    64 entries per column and one open bin; every entry starts untuned."""
+    t = hwpm.hwpm_default_tune_table()
+    assert [float(x) for x in t.max_degree[:5]] == [4.0, 8.0, 16.0, 32.0, 64.0]
+    assert all(p == 0 for p in t.probe) and all(x == 0 for x in t.tile_width)
+    cases = [(0, 0, 0), (100, 0, 0), (100, 400, 0), (100, 401, 1), (100, 800, 1), (100, 1600, 2),
+             (1 << 20, 17825657, 3), (1_000_000, 26_463_592, 3), (10, 641, 5), (10, 640, 4)]
+    for n, nnz, b in cases:
+        assert hwpm.hwpm_tune_bin(t, n, nnz) == b, (n, nnz)

@@ -704,3 +704,105 @@ def test_autotune_keeps_the_result(solver, which):
     assert min(ms, key=ms.get) == (probe, tile)
     assert np.array_equal(perm.cpu().numpy(), ref.perm)
     assert_same(wl, gpu_improve(solver, wl, probe=probe, tile_width=tile), ref)
+
+
+# ---------------------------------------------------------------------------
+# replayed graphs: batches of launches that repeat (8 rounds from the same
+# ring slot, 8 proposal rounds, 8 BFS levels) are captured once per call and
+# replayed; the results equal direct launches and the oracle bit for bit
+
+def _chain(n):
+    """Bidiagonal matrix whose heavier subdiagonal makes the greedy step leave
+    one augmenting path through every column (one BFS phase of n levels)."""
+    nan = np.nan
+    a = np.full((n, n), nan)
+    for j in range(n):
+        a[j, j] = 1.0
+        if j + 1 < n:
+            a[j + 1, j] = 2.0
+    return from_dense(a, name=f"chain{n}")
+
+
+def _ordered(n):
+    """Dense matrix whose rows are heavier the smaller their index: every
+    greedy round matches one row (n proposal rounds)."""
+    a = np.tile(-np.arange(n, dtype=np.float64)[:, None], (1, n))
+    return from_dense(a, name=f"ordered{n}")
+
+
+@pytest.mark.parametrize("case", ["rmat14", "stencil", "chain", "ordered"])
+def test_graph_replay_identical(solver, case):
+    from oracle import oracle_match
+    wl = {"rmat14": lambda: rmat(14, 16, 1014, 2014, 3014, name="rmat_scale14"),
+          "stencil": lambda: stencil27(24, 24, 24, 2107, 3107, name="stencil_24cubed"),
+          "chain": lambda: _chain(61),
+          "ordered": lambda: _ordered(40)}[case]()
+    ref = oracle_improve(wl.n, wl.col_ptr, wl.row_idx, wl.w, wl.planted)
+    for probe in ("p3", "p5"):
+        runs = [gpu_improve(solver, wl, graph=g, **_PROBE_KW[probe]) for g in (True, False, True)]
+        for gpu in runs:
+            assert_same(wl, gpu, ref)
+        if ref.rounds > 6:  # rounds 6..13 form the first replayable batch
+            assert runs[0][2]["graph_launches"] > 0 and runs[1][2]["graph_launches"] == 0
+    mref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w)
+    for g in (True, False):
+        gpu = gpu_match(solver, wl, graph=g)
+        assert_same(wl, gpu, mref)
+        assert (gpu[2]["greedy_rounds"], gpu[2]["mcm_phases"], gpu[2]["mcm_levels"]) == \
+            (mref.greedy_rounds, mref.mcm_phases, mref.mcm_levels)
+        if g and (mref.greedy_rounds > 7 or mref.mcm_levels > 7 or mref.rounds > 6):
+            assert gpu[2]["graph_launches"] > 0
+        if not g:
+            assert gpu[2]["graph_launches"] == 0
+
+
+def test_graph_replay_in_batches(solver):
+    from oracle import oracle_match
+    dev = solver.device
+    wls = [rmat(12, 16, 1012, 2012, 3012, name="rmat_s12"), _chain(61), _ordered(40),
+           small_random(3000, 5, 61)]
+    mats = [(_dev(w.col_ptr, dev), _dev(w.row_idx, dev), _dev(w.w, dev)) for w in wls]
+    outs = []
+    for g in (True, False):
+        perms, totals, items, bst = solver.match_batch(mats, graph=g)
+        outs.append(([p.cpu().numpy() for p in perms], totals, bst))
+        if not g:
+            assert bst["graph_launches"] == 0
+    for b, wl in enumerate(wls):
+        ref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w)
+        for perms, totals, _ in outs:
+            assert np.array_equal(perms[b], ref.perm), wl.name
+            assert np.float64(totals[b]).tobytes() == np.float64(ref.total).tobytes()
+
+
+# ---------------------------------------------------------------------------
+# tuning table by degree bin: batches with default launch options take their
+# bin's tuned configuration; results never change
+
+def test_tune_table_in_batches(solver):
+    from paper_1801_09809_amd import hwpm
+    from oracle import oracle_match
+    dev = solver.device
+    sparse, dense = small_random(30000, 8, 71), stencil27(20, 20, 20, 2108, 3108, name="stencil_20cubed")
+    table = None
+    for wl in (sparse, dense):
+        print(f"[gpu] tune bin of {wl.name}", flush=True)
+        table = solver.autotune_table(_dev(wl.col_ptr, dev), _dev(wl.row_idx, dev), _dev(wl.w, dev),
+                                      _dev(wl.planted, dev), table)
+    bins = {hwpm.hwpm_tune_bin(table, wl.n, wl.nnz) for wl in (sparse, dense)}
+    assert len(bins) == 2 and all(table.probe[b] != 0 for b in bins)
+    solver.set_tune_table(table)
+    try:
+        for members in ([sparse], [dense], [dense, small_random(500, 20, 72)]):
+            n_tot = sum(w.n for w in members)
+            nnz_tot = sum(w.nnz for w in members)
+            b = hwpm.hwpm_tune_bin(table, n_tot, nnz_tot)
+            mats = [(_dev(w.col_ptr, dev), _dev(w.row_idx, dev), _dev(w.w, dev)) for w in members]
+            perms, totals, items, bst = solver.match_batch(mats)
+            if table.probe[b] != 0:
+                assert (bst["probe_used"], bst["tile_used"]) == (table.probe[b], table.tile_width[b])
+            for wl, p, t in zip(members, perms, totals):
+                ref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w)
+                assert np.array_equal(p.cpu().numpy(), ref.perm) and t == ref.total, wl.name
+    finally:
+        solver.set_tune_table(None)

@@ -169,3 +169,85 @@ def test_destroy_finishes_queued_requests():
     for w in wls:
         srv.submit(w.col_ptr, w.row_idx, w.w)
     srv.close()  # joins the workers after the queue drains
+
+
+def test_two_threads_poll_one_ticket():
+    """A ticket belongs to the first poll that waits for it: of two threads
+    that wait on the same ticket, one gets the result (equal to the oracle's)
+    and the other HWPM_EINVAL, and neither touches a released request."""
+    import threading
+    hwpm = _need_gpu()
+    wl = small_random(40000, 6, 91)
+    ref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w)
+    print("[gpu] two pollers on one ticket", flush=True)
+    for rep in range(4):
+        with hwpm.Server(workers=1, max_batch=4, arena_bytes=1 << 30) as srv:
+            ticket = srv.submit(wl.col_ptr, wl.row_idx, wl.w)
+            perms = [np.empty(wl.n, dtype=np.int32) for _ in range(2)]
+            out = [None, None]
+            barrier = threading.Barrier(2)
+
+            def poll(i):
+                barrier.wait()
+                out[i] = hwpm.hwpm_poll(srv.server, ticket, True, perms[i].ctypes.data)
+
+            threads = [threading.Thread(target=poll, args=(i,)) for i in range(2)]
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
+            statuses = sorted(o[0] for o in out)
+            assert statuses == [hwpm.HWPM_EINVAL, hwpm.HWPM_OK], statuses
+            winner = 0 if out[0][0] == hwpm.HWPM_OK else 1
+            assert np.array_equal(perms[winner], ref.perm)
+            assert np.float64(out[winner][1]).tobytes() == np.float64(ref.total).tobytes()
+            srv._n.pop(ticket, None)
+            srv._keep.pop(ticket, None)
+            # the ticket is gone: a third poll is refused too
+            assert hwpm.hwpm_poll(srv.server, ticket, False, None)[0] == hwpm.HWPM_EINVAL
+
+
+def test_destroy_while_a_poll_waits():
+    """A poll that waits while the server is destroyed receives its result
+    before the server's memory is released; polls started after destroy
+    began are refused."""
+    import threading
+    hwpm = _need_gpu()
+    wls = [small_random(60000 + 1000 * k, 6, 92 + k) for k in range(12)]
+    srv = hwpm.Server(workers=1, max_batch=1, arena_bytes=1 << 30)
+    tickets = [srv.submit(w.col_ptr, w.row_idx, w.w) for w in wls]
+    last = wls[-1]
+    perm = np.empty(last.n, dtype=np.int32)
+    out = []
+    th = threading.Thread(target=lambda: out.append(hwpm.hwpm_poll(srv.server, tickets[-1], True,
+                                                                   perm.ctypes.data)))
+    th.start()
+    time.sleep(0.02)
+    print("[gpu] destroy with a waiting poll", flush=True)
+    srv.close()  # finishes the queued requests, waits for the polling thread
+    th.join()
+    # a poll already waiting gets the result; one that came after destroy
+    # began is refused
+    assert out and out[0][0] in (hwpm.HWPM_OK, hwpm.HWPM_EINVAL)
+    print(f"[gpu] waiting poll returned {out[0][0]}", flush=True)
+    if out[0][0] == hwpm.HWPM_OK:
+        ref = oracle_match(last.n, last.col_ptr, last.row_idx, last.w)
+        assert np.array_equal(perm, ref.perm)
+
+
+def test_online_tuning_fills_the_bin():
+    """The server tries each candidate launch configuration on the first
+    batches of a degree bin, then keeps the fastest; every result equals
+    the oracle's, tuned or not."""
+    hwpm = _need_gpu()
+    wls = [small_random(1500 + 37 * k, 8, 300 + k) for k in range(30)]  # 9 entries per column or so
+    print("[gpu] online tuning", flush=True)
+    with hwpm.Server(workers=1, max_batch=1, arena_bytes=1 << 30, tune=True) as srv:
+        tickets = [srv.submit(w.col_ptr, w.row_idx, w.w) for w in wls]
+        for wl, t in zip(wls, tickets):
+            _check(wl, srv.poll(t))
+        table = srv.tune_table()
+    b = hwpm.hwpm_tune_bin(hwpm.hwpm_default_tune_table(), wls[0].n, wls[0].nnz)
+    assert table[b]["probe"] in (3, 4, 5) and table[b]["tile_width"] in (4, 8)
+    assert table[b]["ms_per_mentry"] > 0.0
+    assert all(e["probe"] == 0 for i, e in enumerate(table) if i != b)

@@ -259,11 +259,25 @@ __device__ __forceinline__ int32_t tile_bcast(int32_t v, int src) {
     }
 }
 
-// Largest value over the wave, as a wave-uniform (scalar) value.
-__device__ __forceinline__ int32_t wave_max(int32_t v) {
+// Largest value of the tile, in every lane of the tile.
+template <int T>
+__device__ __forceinline__ int32_t tile_max(int32_t v) {
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
-    return __builtin_amdgcn_readfirstlane(v);
+    for (int sft = 1; sft < T; sft <<= 1) v = max(v, tile_xor<T>(v, sft));
+    return v;
+}
+
+// Largest value over the wave, as a wave-uniform (scalar) value: DPP row
+// shifts give every lane the maximum of its row of 16 up to itself, two row
+// broadcasts carry the rows' maxima into lane 63.  All lanes must be active.
+__device__ __forceinline__ int32_t wave_max(int32_t v) {
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // The per-root values of a tile kernel, read together (one memory round trip).
@@ -362,7 +376,7 @@ __device__ __forceinline__ uint32_t filter_bit1(int32_t c) { return ((uint32_t)c
 __device__ __forceinline__ uint32_t filter_bit2(int32_t c) { return ((uint32_t)c * 0x85EBCA6Bu) >> 26; }
 
 template <int T, int E>
-__global__ __launch_bounds__(256) void k_search_filter(Csc A, Work W, int32_t long_threshold, int slot,
+__global__ __launch_bounds__(256, 8) void k_search_filter(Csc A, Work W, int32_t long_threshold, int slot,
                                                        const int32_t* __restrict__ roots, int32_t cap) {
     if (round_over(W)) return;
     const int lane = threadIdx.x & (T - 1);
@@ -374,14 +388,17 @@ __global__ __launch_bounds__(256) void k_search_filter(Csc A, Work W, int32_t lo
     const bool handoff = r.slen > 0 && (r.slen > T * E || r.rl.y > T * E);
     hand_off(W, slot, blockIdx.x & (kSpread - 1), cap, r.j, handoff && lane == 0);
     const bool search = r.slen > 0 && !handoff;
-    // loads: indices clamped into the segment (the matched entry and the
-    // list's first entry always exist), values past it masked
+    // loads, only as far as the wave's longest suffix and row list go:
+    // indices clamped into the segment (the matched entry and the list's
+    // first entry always exist), values past it masked
+    const int32_t e_lim = (wave_max(search ? r.slen : 0) + T - 1) / T;
+    const int32_t f_lim = (wave_max(search ? r.rl.y : 0) + T - 1) / T;
     int32_t mv[E], rv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int32_t x = lane + T * e;
-        mv[e] = W.mrk[x < r.slen ? r.s0 + x : r.s0 - 1];
-        rv[e] = W.colidx[x < r.rl.y ? r.rl.x + x : r.rl.x];
+        mv[e] = e < e_lim ? W.mrk[x < r.slen ? r.s0 + x : r.s0 - 1] : -1;
+        rv[e] = e < f_lim ? W.colidx[x < r.rl.y ? r.rl.x + x : r.rl.x] : -2;
     }
     uint32_t f1lo = 0, f1hi = 0, f2lo = 0, f2hi = 0;
 #pragma unroll
@@ -411,29 +428,30 @@ __global__ __launch_bounds__(256) void k_search_filter(Csc A, Work W, int32_t lo
         if ((w1 >> (b1 & 31)) & (w2 >> (b2 & 31)) & 1u) pending |= 1u << e;
     }
     Cand b{0.0, kNoPos, -1, -1};
-    if (__ballot(pending != 0)) {  // wave-uniform
-        // the tile's whole row list in every lane: place x = src + T * f
-        int32_t all[T * E];
+    while (__ballot(pending != 0)) {  // wave-uniform: one passed probe per lane at a time
+        const int e = pending ? __builtin_ctz(pending) : -1;
+        pending &= pending - 1;
+        int32_t mi = -1;
 #pragma unroll
-        for (int f = 0; f < E; ++f)
+        for (int u = 0; u < E; ++u)
+            if (u == e) mi = mv[u];
+        // the tile's probes, each compared by every lane with its own part
+        // of the row list; the matching place comes back to the probe's lane
+        int32_t q = -1;
 #pragma unroll
-            for (int src = 0; src < T; ++src) all[src + T * f] = tile_bcast<T>(rv[f], src);
-        while (__ballot(pending != 0)) {  // wave-uniform: one passed probe per lane at a time
-            const int e = pending ? __builtin_ctz(pending) : -1;
-            pending &= pending - 1;
-            int32_t mi = -1;
+        for (int src = 0; src < T; ++src) {
+            const int32_t ps = tile_bcast<T>(mi, src);
+            int32_t xs = -1;
 #pragma unroll
-            for (int u = 0; u < E; ++u)
-                if (u == e) mi = mv[u];
-            int32_t q = -1;
-#pragma unroll
-            for (int x = 0; x < T * E; ++x)
-                if (all[x] == mi) q = x;
-            if (q >= 0) {
-                const int32_t k = r.s0 + lane + T * e;
-                const int64_t p = W.cscpos ? (int64_t)W.cscpos[r.rl.x + q] : find_row(A.col_ptr, A.row_idx, mi, W.mc[r.j]);
-                if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[r.j]), k, mi, p);
-            }
+            for (int f = 0; f < E; ++f)
+                if (rv[f] == ps) xs = lane + T * f;
+            xs = tile_max<T>(xs);
+            if (lane == src) q = xs;
+        }
+        if (q >= 0) {
+            const int32_t k = r.s0 + lane + T * e;
+            const int64_t p = W.cscpos ? (int64_t)W.cscpos[r.rl.x + q] : find_row(A.col_ptr, A.row_idx, mi, W.mc[r.j]);
+            if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[r.j]), k, mi, p);
         }
     }
     if (__ballot(b.k != kNoPos)) reduce_best<T>(b);  // wave-uniform: most waves have no candidate

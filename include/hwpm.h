@@ -226,6 +226,27 @@ int hwpm_improve(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32
                  double* total_out, const hwpm_options* opt, hwpm_stats* stats,
                  void* workspace, size_t workspace_bytes);
 
+/* ---- allocation-free form ---------------------------------------------
+ * hwpm_improve for callers that cannot allocate device memory and cannot
+ * bring a workspace of their own (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Its workspace is a fixed
+ * device array of HWPM_STATIC_SCRATCH_BYTES that the library holds on every
+ * GPU it runs on until the process ends (its address is taken in
+ * hwpm_create).  The call allocates nothing: no hipMalloc, hipFree or
+ * allocating library routine.  Inputs and outputs are the caller's, as in
+ * hwpm_improve.
+ *
+ * Every call on one GPU uses that GPU's one array, whose contents are
+ * scratch between calls: calls that overlap on one GPU (from several
+ * handles, threads or streams) race and must be serialised by the caller.
+ * Errors as hwpm_improve, plus HWPM_ETOOBIG when
+ * hwpm_workspace_bytes(n, nnz) exceeds HWPM_STATIC_SCRATCH_BYTES (outputs
+ * untouched), and HWPM_EDEVICE if the array's device address was not
+ * available when the handle was created. */
+#define HWPM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+int hwpm_improve_static(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
+                        double* total_out, const hwpm_options* opt, hwpm_stats* stats);
+
 /* The whole HWPM pipeline (Section 5.1): a greedy maximal matching, then a
  * maximum-cardinality matching by multi-source BFS phases (both with the
  * heavy-edge tie-break of Section 5.2 unless opt->mcm_plain), then the rounds

@@ -2,6 +2,7 @@
 // workspace carve-up, and the host round loop that launches the kernels of
 // hwpm_kernels.hip and reads back two counters per round.
 #include <chrono>
+#include <mutex>
 #include <new>
 #include <vector>
 #include <string.h>
@@ -15,6 +16,7 @@ struct hwpm_handle_s {
     int device;
     hipStream_t stream;
     int cus;
+    void* scratch;        // this device's copy of the static workspace (hwpm_improve_static), or null
     hipStream_t cap;      // private stream that repeated batches of launches are captured on
     bool has_tune;        // batches resolve default launch configurations from `tune`
     hwpm_tune_table tune;
@@ -36,6 +38,32 @@ constexpr int kHostScalar = 64;
 constexpr int kHostRounds = 256;
 constexpr size_t kHostBytes = (kHostRounds + 3 * kMaxRoundStats) * sizeof(int32_t);
 constexpr int64_t kMaxNnz = (int64_t)1 << 40;
+
+// The workspace of hwpm_improve_static: a fixed device array, one copy per
+// GPU, held until the process ends.  Host code never uses the array's name as
+// an address: the device address of each GPU's copy is looked up once, with
+// that device current, and kept in g_scratch.
+constexpr size_t kStaticScratchBytes = HWPM_STATIC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (which is `device`), or
+// null if the runtime cannot give it.
+void* static_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[device]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch[device] = ptr;
+    }
+    return g_scratch[device];
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -637,6 +665,7 @@ int hwpm_create(hwpm_handle* out, int device, void* stream) {
     h->device = device;
     h->stream = (hipStream_t)stream;
     h->host = nullptr;
+    h->scratch = static_scratch(device);  // once per device (the device is current here)
     h->cap = nullptr;
     h->has_tune = false;
     hwpm_default_tune_table(&h->tune);
@@ -737,6 +766,24 @@ int hwpm_improve(hwpm_handle h, const hwpm_csc* Ain, const int32_t* mate_in, int
     S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
     if (stats) *stats = S;
     return HWPM_OK;
+}
+
+int hwpm_improve_static(hwpm_handle h, const hwpm_csc* A, const int32_t* mate_in, int32_t* perm_out,
+                        double* total_out, const hwpm_options* opt, hwpm_stats* stats) {
+    if (!h) return HWPM_EINVAL;
+    const int st = check_csc_args(A);
+    if (st != HWPM_OK) return st;
+    if (workspace_layout(A->n, A->nnz, nullptr, nullptr) > kStaticScratchBytes) return HWPM_ETOOBIG;
+    if (!h->scratch) return HWPM_EDEVICE;
+    // the same solve as hwpm_improve, with the static array as its workspace
+    // and no graph instantiation; nothing on this path allocates (the
+    // library's kernels, stream-ordered copies and fills, the handle's pinned
+    // buffer and events)
+    hwpm_options o;
+    hwpm_default_options(&o);
+    if (opt) o = *opt;
+    o.graph = 0;
+    return hwpm_improve(h, A, mate_in, perm_out, total_out, &o, stats, h->scratch, kStaticScratchBytes);
 }
 
 int hwpm_match(hwpm_handle h, const hwpm_csc* Ain, int32_t* perm_out, double* total_out,

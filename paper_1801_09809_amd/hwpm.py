@@ -27,13 +27,14 @@ HWPM_EDEVICE = -7
 HWPM_EINTERNAL = -8
 HWPM_PENDING = 1
 MAX_ROUND_STATS = 512
+STATIC_SCRATCH_BYTES = 128 << 20  # HWPM_STATIC_SCRATCH_BYTES
 TUNE_CANDIDATES = 12
 TUNE_CONFIGS = ((1, 4), (1, 8), (1, 16), (1, 32), (1, 64), (3, 4), (3, 8), (3, 16), (3, 32), (4, 4),
                 (5, 4), (5, 8))
 
 EXPORTED = (
     "hwpm_default_options", "hwpm_strerror", "hwpm_create", "hwpm_destroy",
-    "hwpm_workspace_bytes", "hwpm_check_csc", "hwpm_improve", "hwpm_match",
+    "hwpm_workspace_bytes", "hwpm_check_csc", "hwpm_improve", "hwpm_improve_static", "hwpm_match",
     "hwpm_autotune", "hwpm_batch_workspace_bytes", "hwpm_improve_batch", "hwpm_match_batch",
     "hwpm_server_default_options", "hwpm_server_create", "hwpm_server_destroy",
     "hwpm_submit", "hwpm_poll", "hwpm_server_get_stats", "hwpm_server_get_tune_table",
@@ -222,6 +223,10 @@ def load_library(path: str = LIB_PATH):
         lib.hwpm_improve.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, vp,
                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(hwpm_options),
                                      ctypes.POINTER(hwpm_stats), vp, ctypes.c_size_t]
+        lib.hwpm_improve_static.restype = ctypes.c_int
+        lib.hwpm_improve_static.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, vp,
+                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(hwpm_options),
+                                            ctypes.POINTER(hwpm_stats)]
         lib.hwpm_autotune.restype = ctypes.c_int
         lib.hwpm_autotune.argtypes = [vp, ctypes.POINTER(hwpm_csc), vp, vp, ctypes.POINTER(hwpm_options),
                                       ctypes.POINTER(ctypes.c_float), vp, ctypes.c_size_t]
@@ -312,6 +317,21 @@ def hwpm_improve(handle: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: i
         ctypes.byref(options) if options is not None else None,
         ctypes.byref(stats) if stats is not None else None,
         ctypes.c_void_p(ws_ptr), ctypes.c_size_t(ws_bytes))
+    return st, total.value, stats
+
+
+def hwpm_improve_static(handle: int, n: int, nnz: int, col_ptr_ptr: int, row_idx_ptr: int,
+                        weight_ptr: int, mate_in_ptr: int, perm_out_ptr: int,
+                        options: hwpm_options | None = None, want_stats: bool = True):
+    """hwpm_improve on the library's static workspace.  Returns (status, total, stats or None)."""
+    A = _csc(n, nnz, col_ptr_ptr, row_idx_ptr, weight_ptr)
+    total = ctypes.c_double(0.0)
+    stats = hwpm_stats() if want_stats else None
+    st = load_library().hwpm_improve_static(
+        ctypes.c_void_p(handle), ctypes.byref(A), ctypes.c_void_p(mate_in_ptr),
+        ctypes.c_void_p(perm_out_ptr), ctypes.byref(total),
+        ctypes.byref(options) if options is not None else None,
+        ctypes.byref(stats) if stats is not None else None)
     return st, total.value, stats
 
 

@@ -28,7 +28,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 # the sources the search stage is compiled from (their hash keys the traffic record)
-SEARCH_SOURCES = ("hwpm_search.hip", "hwpm_device.h", "hwpm_internal.h")
+SEARCH_SOURCES = ("hwpm_search.hip", "hwpm_device.h", "hwpm_hash.h", "hwpm_internal.h")
 
 
 def search_bytes(nnz: int, n: int) -> float:
@@ -64,9 +64,10 @@ def load_traffic(kernel: str, workload_name: str, probe: int):
     return None
 
 
-def cpu_baseline(wl, min_seconds: float = 10.0) -> dict:
+def cpu_baseline(wl, min_seconds: float = 10.0):
     """The oracle (single thread) on the same workload from the same matching:
-    whole solves repeated until about min_seconds of CPU time have passed."""
+    whole solves repeated until about min_seconds of CPU time have passed.
+    Returns the baseline record and the oracle's result."""
     from oracle import oracle_improve
     t0 = time.perf_counter()
     solves = 0
@@ -76,50 +77,40 @@ def cpu_baseline(wl, min_seconds: float = 10.0) -> dict:
         dt = time.perf_counter() - t0
         if dt >= min_seconds or solves >= 50:
             break
-    return {"value": wl.nnz * ref.rounds * solves / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": f"{solves} full solves of {wl.name} ({ref.rounds} rounds each, {dt:.1f} s)",
-            "rounds": ref.rounds}
+    return ({"value": wl.nnz * ref.rounds * solves / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+             "sample": f"{solves} full solves of {wl.name} ({ref.rounds} rounds each, {dt:.1f} s)",
+             "rounds": ref.rounds, **host_cpu()}, ref)
+
+
+def _bits(x: float) -> str:
+    import numpy as np
+    return np.float64(x).tobytes().hex()
+
+
+def _perm_digest(perm) -> str:
+    import hashlib
+
+    import numpy as np
+    return hashlib.sha256(np.ascontiguousarray(perm, dtype=np.int32).tobytes()).hexdigest()
+
+
+_ORACLE_CHECK = True
 
 
 def _gen_serving(index: int):
+    """Matrix `index` of the serving stream and, with the oracle check on,
+    the oracle's result for it: (status, permutation digest, total bits,
+    oracle seconds)."""
     from workloads import serving_matrix
     wl = serving_matrix(index)
-    return wl.col_ptr, wl.row_idx, wl.w
-
-
-def serving_stream(count: int):
-    """Matrices 0..count-1 of the serving stream, generated by a process pool."""
-    import multiprocessing as mp
-    procs = max(1, min(16, os.cpu_count() or 1))
-    with mp.get_context("fork").Pool(procs) as pool:
-        return pool.map(_gen_serving, range(count), chunksize=8)
-
-
-_SERVING_MATS = None
-
-
-def _oracle_solve(index: int) -> int:
-    from oracle import oracle_match
-    cp, ri, w = _SERVING_MATS[index]
-    return oracle_match(cp.size - 1, cp, ri, w).status
-
-
-def serving_cpu_baseline(mats, sample: int) -> dict:
-    """The oracle's whole solve (Phase I + rounds) on the first `sample`
-    matrices of the serving stream, one matrix per worker process."""
-    import multiprocessing as mp
-    global _SERVING_MATS
-    _SERVING_MATS = mats
-    procs = max(1, min(16, os.cpu_count() or 1))
-    count = min(sample, len(mats))
-    t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(procs) as pool:
-        status = pool.map(_oracle_solve, range(count), chunksize=1)
-    dt = time.perf_counter() - t0
-    _SERVING_MATS = None
-    assert all(st == 0 for st in status)
-    return {"value": count / dt, "unit": "solves/s", "cores": procs, "kind": "oracle",
-            "sample": f"first {count} matrices of the serving stream, one per worker process ({dt:.1f} s)"}
+    rec = None
+    if _ORACLE_CHECK:
+        from oracle import oracle_match
+        t0 = time.perf_counter()
+        ref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w)
+        dt = time.perf_counter() - t0
+        rec = (int(ref.status), _perm_digest(ref.perm) if ref.status == 0 else "", _bits(ref.total), dt)
+    return wl.col_ptr, wl.row_idx, wl.w, rec
 
 
 def _pct(x, q):
@@ -127,32 +118,110 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
 
 
-def serving_bench(args, dev, mats) -> dict:
+def host_threads() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def host_cpu() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "threads_available": host_threads(), "nproc": os.cpu_count()}
+
+
+def serving_stream(count: int, oracle_check: bool):
+    """Matrices 0..count-1 of the serving stream, generated (and solved by
+    the oracle) in a pool of worker processes forked before the GPU is used.
+    Returns (list of (col_ptr, row_idx, w, oracle record), seconds, processes)."""
+    import multiprocessing as mp
+    global _ORACLE_CHECK
+    _ORACLE_CHECK = oracle_check
+    procs = max(1, min(16, host_threads()))
+    t0 = time.perf_counter()
+    with mp.get_context("fork").Pool(procs) as pool:
+        out = pool.map(_gen_serving, range(count), chunksize=4)
+    return out, time.perf_counter() - t0, procs
+
+
+def pack_stream(gen, pinned: bool):
+    """Copy the stream into page-locked host buffers of 1 GiB (each request's
+    arrays inside one buffer), as from a receive path that lands requests in
+    pinned memory; the generated arrays are released as they are copied.
+    Returns per-request (numpy views, torch views)."""
+    import numpy as np
+    import torch
+    chunk = 1 << 30
+    bufs, cur, off = [], None, 0
+    out = []
+
+    def take(nbytes):
+        nonlocal cur, off
+        nbytes = (nbytes + 255) & ~255
+        if cur is None or off + nbytes > cur.numel():
+            cur = torch.empty(max(chunk, nbytes), dtype=torch.uint8, pin_memory=pinned)
+            bufs.append(cur)
+            off = 0
+        t = cur[off:off + nbytes]
+        off += nbytes
+        return t
+
+    for k in range(len(gen)):
+        cp, ri, w, _ = gen[k]
+        views = []
+        for a, dt in ((cp, torch.int64), (ri, torch.int32), (w, torch.float64)):
+            t = take(max(a.nbytes, 1))[:a.nbytes].view(dt)
+            t.numpy()[:] = a
+            views.append(t)
+        out.append((tuple(v.numpy() for v in views), tuple(views)))
+        gen[k] = (None, None, None, gen[k][3])
+    return out, bufs
+
+
+def serving_bench(args, dev, gen, gen_seconds, procs) -> dict:
     """Serving stream: plain one-at-a-time solves (host CSC -> device -> hwpm_match
     -> host permutation, in arrival order) against the request loop
     (hwpm_submit / hwpm_poll, continuous batching).  Both see the same
     matrices; latency runs from the scheduled arrival to the permutation on
-    the host.  Every served result must equal the plain result bit for bit."""
+    the host.  Every result of both forms is compared with the oracle's."""
     import threading
 
     import numpy as np
-    import torch
     from paper_1801_09809_amd import hwpm
     from workloads import poisson_arrivals
 
-    count = len(mats)
-    nnz_tot = sum(int(m[1].size) for m in mats)
+    count = len(gen)
+    oracle = [g[3] for g in gen]
+    check_oracle = oracle[0] is not None
+    nnz_tot = sum(int(g[1].size) for g in gen)
+    n_tot = sum(int(g[0].size) - 1 for g in gen)
+    t_pack = time.perf_counter()
+    packed, bufs = pack_stream(gen, bool(args.serving_pinned))
+    print(f"[bench] serving stream packed into {len(bufs)} page-locked buffers in "
+          f"{time.perf_counter() - t_pack:.1f} s", file=sys.stderr, flush=True)
+    host = [p[0] for p in packed]
+    tens = [p[1] for p in packed]
     solver = hwpm.Solver(0)
-    if args.serving_pinned:
-        # requests arrive in page-locked host buffers (as from a network or
-        # storage receive path), so host-to-device copies run at DMA speed
-        pinned = [tuple(torch.from_numpy(a).pin_memory() for a in m) for m in mats]
-        mats = [tuple(t.numpy() for t in m) for m in pinned]
-    else:
-        pinned = [tuple(torch.from_numpy(a) for a in m) for m in mats]
+    mismatches = {"plain": 0, "served": 0}
+
+    def same_as_oracle(k, st, perm, total) -> bool:
+        if not check_oracle:
+            return True
+        ost, odig, obits, _ = oracle[k]
+        if st != ost:
+            return False
+        return st != 0 or (_perm_digest(perm) == odig and _bits(total) == obits)
 
     def plain(k):
-        cp, ri, w = pinned[k]
+        cp, ri, w = tens[k]
         # validated on the device, as the request loop does
         res = solver.match(cp.to(dev, non_blocking=True), ri.to(dev, non_blocking=True),
                            w.to(dev, non_blocking=True), check_csc=True)
@@ -160,95 +229,163 @@ def serving_bench(args, dev, mats) -> dict:
 
     for k in range(min(8, count)):  # warm-up
         plain(k)
-    # plain capacity: back to back, arrival order
+    # plain capacity: back to back, arrival order, every result checked
     t0 = time.perf_counter()
-    ref = [plain(k) for k in range(count)]
+    plain_out = [plain(k) for k in range(count)]
     plain_rate = count / (time.perf_counter() - t0)
-    print(f"[bench] plain back-to-back: {plain_rate:.1f} solves/s", file=sys.stderr, flush=True)
+    for k, (perm, total) in enumerate(plain_out):
+        if not same_as_oracle(k, 0, perm, total):
+            mismatches["plain"] += 1
+    del plain_out
+    print(f"[bench] plain back-to-back: {plain_rate:.1f} solves/s ({count} requests)", file=sys.stderr, flush=True)
 
     srv_kw = dict(workers=args.serving_workers, max_batch=args.serving_max_batch,
                   arena_bytes=args.serving_arena_gib << 30)
-    identical = True
 
-    def check(k, res):
-        nonlocal identical
-        st, perm, total, _ = res
-        if st != hwpm.HWPM_OK or not np.array_equal(perm, ref[k][0]) or \
-                np.float64(total).tobytes() != np.float64(ref[k][1]).tobytes():
-            identical = False
-
-    def served_run(arrivals):
-        """Submit at the arrival times (None: all at once); returns latencies (ms),
-        the makespan and the server statistics."""
-        lat = [0.0] * count
+    def served_run(m, arrivals, check=False):
+        """Submit requests 0..m-1 at the arrival times (None: all at once);
+        returns latencies (ms), the makespan and the server statistics."""
+        lat = [0.0] * m
         with hwpm.Server(**srv_kw) as srv:
-            tickets = [None] * count
-            t_sub = [0.0] * count
+            tickets = [None] * m
+            t_sub = [0.0] * m
             start = time.perf_counter()
 
             def submitter():
-                for k in range(count):
+                for k in range(m):
                     if arrivals is not None:
                         d = start + arrivals[k] - time.perf_counter()
                         if d > 0:
                             time.sleep(d)
                     t_sub[k] = time.perf_counter()
-                    tickets[k] = srv.submit(*mats[k])
+                    tickets[k] = srv.submit(*host[k])
             th = threading.Thread(target=submitter)
             th.start()
             last = start
-            for k in range(count):
+            for k in range(m):
                 while tickets[k] is None:
                     time.sleep(0.0002)
-                res = srv.poll(tickets[k])
-                check(k, res)
+                st, perm, total, info = srv.poll(tickets[k])
+                if check and not same_as_oracle(k, st, perm, total):
+                    mismatches["served"] += 1
                 due = start + (arrivals[k] if arrivals is not None else 0.0)
-                lat[k] = 1e3 * (t_sub[k] - due) + res[3]["latency_ms"]
-                last = max(last, t_sub[k] + res[3]["latency_ms"] / 1e3)
+                lat[k] = 1e3 * (t_sub[k] - due) + info["latency_ms"]
+                last = max(last, t_sub[k] + info["latency_ms"] / 1e3)
             th.join()
             st = srv.stats()
         return lat, last - start, st
 
-    def plain_run(arrivals):
-        lat = [0.0] * count
+    def plain_run(m, arrivals):
+        lat = [0.0] * m
         start = time.perf_counter()
-        for k in range(count):
+        for k in range(m):
             d = start + arrivals[k] - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            perm, total = plain(k)
+            plain(k)
             lat[k] = 1e3 * (time.perf_counter() - (start + arrivals[k]))
         return lat, time.perf_counter() - start
 
-    served_run(None)  # warm-up of the worker streams
-    lat_sat, span_sat, st_sat = served_run(None)
+    served_run(min(count, 1000), None)  # warm-up of the worker streams
+    lat_sat, span_sat, st_sat = served_run(count, None, check=True)
     served_rate = count / span_sat
     print(f"[bench] served back-to-back: {served_rate:.1f} solves/s, {st_sat['batches']} batches",
           file=sys.stderr, flush=True)
-    sweep = []
-    for f in args.serving_rates:
+
+    def open_loop(m, f, check=False):
         rate = f * plain_rate
-        arr = poisson_arrivals(count, rate)
-        pl, pspan = plain_run(arr)
-        sl, sspan, sst = served_run(arr)
-        row = {"load": f, "rate": rate,
-               "plain": {"solves_per_s": count / pspan, "p50_ms": _pct(pl, 50), "p99_ms": _pct(pl, 99)},
-               "served": {"solves_per_s": count / sspan, "p50_ms": _pct(sl, 50), "p99_ms": _pct(sl, 99),
+        arr = poisson_arrivals(m, rate)
+        pl, pspan = plain_run(m, arr)
+        sl, sspan, sst = served_run(m, arr, check=check)
+        row = {"load": f, "rate": rate, "requests": m,
+               "plain": {"solves_per_s": m / pspan, "p50_ms": _pct(pl, 50), "p99_ms": _pct(pl, 99)},
+               "served": {"solves_per_s": m / sspan, "p50_ms": _pct(sl, 50), "p99_ms": _pct(sl, 99),
                           "batches": sst["batches"], "max_batch": sst["max_batch_seen"],
                           "max_running": sst["max_running"]}}
-        print(f"[bench] load {f}: plain p50/p99 {row['plain']['p50_ms']:.2f}/{row['plain']['p99_ms']:.2f} ms, "
-              f"served p50/p99 {row['served']['p50_ms']:.2f}/{row['served']['p99_ms']:.2f} ms",
-              file=sys.stderr, flush=True)
-        sweep.append(row)
+        print(f"[bench] load {f} ({m} requests): plain p50/p99 {row['plain']['p50_ms']:.2f}/"
+              f"{row['plain']['p99_ms']:.2f} ms, served p50/p99 {row['served']['p50_ms']:.2f}/"
+              f"{row['served']['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+        return row
+
+    sweep_m = min(count, args.serving_sweep_requests)
+    sweep = [open_loop(sweep_m, f) for f in args.serving_rates]
+    full = open_loop(count, args.serving_full_load, check=True) if args.serving_full_load > 0 else None
     solver.close()
-    return {"metric": "batched solves/s + p99 latency vs plain", "requests": count,
-            "nonzeros": nnz_tot,
-            "workload": "serving stream: n = round(10^U(2,5)), 1/2 random (8 per column + diagonal), "
-                        "1/2 27-point stencil cut to n; Poisson arrivals at load x plain capacity",
-            "server": srv_kw, "pinned_host_buffers": bool(args.serving_pinned),
-            "plain_solves_per_s": plain_rate, "served_solves_per_s": served_rate,
-            "speedup": served_rate / plain_rate, "open_loop": sweep,
-            "identical_to_plain": identical}
+    del bufs
+    out = {"metric": "batched solves/s + p99 latency vs plain", "requests": count,
+           "columns": n_tot, "nonzeros": nnz_tot,
+           "workload": "serving stream: n = round(10^U(2,5)), 1/2 random (8 per column + diagonal), "
+                       "1/2 27-point stencil cut to n; Poisson arrivals at load x plain capacity",
+           "server": srv_kw, "pinned_host_buffers": bool(args.serving_pinned),
+           "plain_solves_per_s": plain_rate, "served_solves_per_s": served_rate,
+           "speedup": served_rate / plain_rate,
+           "open_loop_full_stream": full,
+           "open_loop_sweep": sweep,
+           "oracle_checked": check_oracle,
+           "oracle_identical": (mismatches["plain"] == 0 and mismatches["served"] == 0) if check_oracle else None,
+           "oracle_mismatches": mismatches if check_oracle else None}
+    if check_oracle:
+        t_or = sum(r[3] for r in oracle)
+        out["cpu_baseline"] = {"value": count / (t_or / procs), "unit": "solves/s", "cores": procs,
+                               "kind": "oracle", **host_cpu(),
+                               "sample": f"all {count} matrices of the stream, one per worker process "
+                                         f"({t_or:.1f} s of oracle time over {procs} processes; generation "
+                                         f"and oracle together {gen_seconds:.1f} s)"}
+    return out
+
+
+def quality_small(solver, dev) -> dict:
+    """The weight of the whole pipeline's matching on the small random
+    workload against the optimum perfect matching (a library assignment
+    solver), as the paper reports it (Section 6.2: matching weight over the
+    optimum, sum objective on the equilibrated matrix), and the gap for the
+    sum-of-logs weights as configured (the log of the product ratio)."""
+    import numpy as np
+    import torch
+    from scipy.optimize import linear_sum_assignment
+    from workloads import equilibrated, with_weights, workload
+
+    wl = workload(0)
+    eq = equilibrated(wl)
+    cases = {"option_a_equilibrated": with_weights(eq, np.exp(eq.w), "_optA"), "option_b_log": wl}
+    out = {"workload": wl.name}
+    for name, m in cases.items():
+        res = solver.match(torch.from_numpy(m.col_ptr).to(dev), torch.from_numpy(m.row_idx).to(dev),
+                           torch.from_numpy(m.w).to(dev))
+        cols = np.repeat(np.arange(m.n), np.diff(m.col_ptr))
+        big = 1e6
+        cost = np.full((m.n, m.n), -big)
+        cost[m.row_idx, cols] = m.w
+        r, c = linear_sum_assignment(cost, maximize=True)
+        assert (cost[r, c] > -big / 2).all()
+        opt = float(np.sum(cost[r, c]))
+        # ratio of the matched weight sums; for log weights the gap is the
+        # log of the ratio of the matched products
+        rec = {"hwpm": res.total, "optimum": opt, "ratio": res.total / opt}
+        if not name.startswith("option_a"):
+            rec["log_gap"] = opt - res.total
+        out[name] = rec
+    return out
+
+
+def copy_ceiling(dev, mib: int = 2048, reps: int = 5) -> float:
+    """Achievable HBM bandwidth: a device-to-device copy of `mib` MiB (read +
+    write bytes over the copy time), far larger than the 256 MB cache in
+    front of HBM."""
+    import torch
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * (mib << 20) / (ms / 1e3) / 1e9
 
 
 def main(argv=None) -> int:
@@ -259,8 +396,8 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", type=int, default=1)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--probe", type=int, default=0,
-                    help="0: tuned; 1 column search, 2 row lists, 3 chunked row lists, 4 vector loads, "
-                         "5 chunked lists without positions")
+                    help="0: tuned; 1 column search, 2 row lists, 3 row lists in LDS hash sets, "
+                         "4 row lists compared across lanes, 5 hash sets over lists without positions")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the launch-configuration tuner (probe 3 unless --probe/--tile are given)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -271,15 +408,21 @@ def main(argv=None) -> int:
     ap.add_argument("--copy-calib-mib", type=int, default=0,
                     help="after the timed steps, copy a buffer of this many MiB three times "
                          "(a device copy kernel of known size, to scale rocprofv3 byte counters)")
-    ap.add_argument("--serving-requests", type=int, default=1000,
+    ap.add_argument("--serving-requests", type=int, default=10000,
                     help="matrices of the serving stream (0 = skip the serving measurement)")
+    ap.add_argument("--serving-sweep-requests", type=int, default=2000,
+                    help="requests of each point of the open-loop load sweep (the first ones of the stream)")
+    ap.add_argument("--serving-full-load", type=float, default=1.0,
+                    help="offered load of the open-loop run over the whole stream (0 = skip)")
+    ap.add_argument("--no-oracle-check", action="store_true",
+                    help="skip the oracle's solve of every serving request (and the serving CPU baseline)")
     ap.add_argument("--serving-workers", type=int, default=4)
     ap.add_argument("--serving-max-batch", type=int, default=64)
     ap.add_argument("--serving-arena-gib", type=int, default=16)
     ap.add_argument("--serving-pinned", type=int, default=1,
                     help="1: the serving stream's host arrays are page-locked (both paths)")
     ap.add_argument("--serving-rates", type=lambda t: [float(x) for x in t.split(",")],
-                    default=[0.5, 1.0, 2.0, 3.0], help="offered loads, in units of the plain capacity")
+                    default=[0.5, 0.8, 1.0, 1.2, 2.0], help="offered loads, in units of the plain capacity")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}): the solve is not sharded "
@@ -291,18 +434,14 @@ def main(argv=None) -> int:
     from paper_1801_09809_amd import hwpm
     from workloads import workload
 
-    mats = None
+    gen = None
     if args.serving_requests > 0:
-        # generated before the GPU is touched: the pool forks this process
-        t_gen = time.perf_counter()
-        mats = serving_stream(args.serving_requests)
-        print(f"[bench] serving stream: {len(mats)} matrices, {sum(m[1].size for m in mats)} nonzeros, "
-              f"generated in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
-        serving_cpu = None
-        if not args.no_cpu_baseline:
-            serving_cpu = serving_cpu_baseline(mats, 400)
-            print(f"[bench] serving oracle baseline: {serving_cpu['value']:.1f} solves/s on "
-                  f"{serving_cpu['cores']} processes", file=sys.stderr, flush=True)
+        # generated (and solved by the oracle) before the GPU is touched: the
+        # pool forks this process
+        gen, gen_s, gen_procs = serving_stream(args.serving_requests, not args.no_oracle_check)
+        print(f"[bench] serving stream: {len(gen)} matrices, {sum(g[1].size for g in gen)} nonzeros, "
+              f"generated{' and solved by the oracle' if not args.no_oracle_check else ''} in {gen_s:.1f} s "
+              f"on {gen_procs} processes", file=sys.stderr, flush=True)
     wl = workload(args.workload)
     print(f"[bench] workload {args.workload}: {wl.name} n={wl.n} nnz={wl.nnz}", file=sys.stderr, flush=True)
     dev = torch.device("cuda", 0)
@@ -352,6 +491,8 @@ def main(argv=None) -> int:
         results.append(step())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    perm_timed = perm.cpu().numpy().copy()  # the last timed step's result, for the oracle check
+    total_timed = results[-1].total
     stats = [r.stats for r in results]  # converted after the timed region
     ms_step = 1e3 * dt / args.steps
     rounds = stats[0]["rounds"]
@@ -383,12 +524,17 @@ def main(argv=None) -> int:
         alg = search_bytes(wl.nnz, wl.n)
         achieved = alg / (launch_ms / 1e3) / 1e9
         traffic = load_traffic("search_stage", wl.name, probe)
+        ceiling = copy_ceiling(dev)
+        print(f"[bench] device copy ceiling {ceiling:.0f} GB/s", file=sys.stderr, flush=True)
         out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                           "copy_ceiling": ceiling, "frac_of_copy_ceiling": achieved / ceiling,
+                           "bytes_basis": "achieved = algorithmic bytes (8 per entry + 16 per column) over the "
+                                          "stage's mean time per round; traffic = calibrated HBM counters",
                            "kernel": "search stage, Steps A-C (" + {
-                               1: "k_search_short", 2: "k_search_rows", 3: "k_search_chunk + k_search_medium",
-                               4: "k_search_vec + k_search_medium",
-                               5: "k_search_chunk + k_search_medium, lists without positions"}[probe] + ")",
+                               1: "k_search_short", 2: "k_search_rows", 3: "k_search_filter + k_search_medium",
+                               4: "k_search_chunk + k_search_medium",
+                               5: "k_search_filter + k_search_medium, lists without positions"}[probe] + ")",
                            "algorithmic_bytes_per_launch": alg, "avg_launch_ms": launch_ms}
         out["search_edges_per_s"] = edges / (ms_search / 1e3)
         staged = [step(timing=1).stats for _ in range(max(3, args.warmup))]
@@ -415,14 +561,23 @@ def main(argv=None) -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calib_bytes"] = src.numel() * 4
+    out["quality"] = quality_small(solver, dev)
     solver.close()
     if args.serving_requests > 0:
-        out["serving"] = serving_bench(args, dev, mats)
-        if serving_cpu is not None:
-            out["serving"]["cpu_baseline"] = serving_cpu
+        out["serving"] = serving_bench(args, dev, gen, gen_s, gen_procs)
+        print(f"[bench] serving results identical to the oracle: {out['serving']['oracle_identical']}",
+              file=sys.stderr, flush=True)
     gc.enable()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl)
+        base, ref = cpu_baseline(wl)
+        out["cpu_baseline"] = base
+        # the timed solve's output against the oracle's, bit for bit
+        out["oracle_identical"] = bool(np.array_equal(perm_timed, ref.perm)
+                                       and _bits(total_timed) == _bits(ref.total)
+                                       and stats[0]["round_applied"] == ref.round_applied
+                                       and stats[0]["round_candidates"] == ref.round_candidates)
+        print(f"[bench] headline result identical to the oracle: {out['oracle_identical']}",
+              file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
     return 0
 

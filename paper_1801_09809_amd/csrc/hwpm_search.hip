@@ -375,19 +375,52 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
 __device__ __forceinline__ uint32_t filter_bit1(int32_t c) { return ((uint32_t)c * 0x9E3779B1u) >> 26; }
 __device__ __forceinline__ uint32_t filter_bit2(int32_t c) { return ((uint32_t)c * 0x85EBCA6Bu) >> 26; }
 
+// A root whose suffix and row list exceed the tile but fit the wave's 64
+// lanes: the whole wave searches it, one suffix entry and one list entry per
+// lane, every list entry broadcast in turn.  j is wave-uniform, so its values
+// come in through scalar loads; all lanes must be active.
+__device__ __forceinline__ void search_wide(const Csc& A, const Work& W, int32_t j, int l64) {
+    const int32_t s0 = W.pm[j] + 1, slen = W.cp32[j + 1] - s0;
+    const int2 rl = W.rsl[j];
+    const int32_t mi = l64 < slen ? W.mrk[s0 + l64] : -1;
+    const int32_t cv = l64 < rl.y ? W.colidx[rl.x + l64] : -2;
+    int32_t q = -1;
+    for (int32_t x = 0; x < rl.y; ++x)  // wave-uniform trip count
+        if (__builtin_amdgcn_readlane(cv, x) == mi) q = x;
+    Cand b{0.0, kNoPos, -1, -1};
+    if (q >= 0) {
+        const int32_t k = s0 + l64;
+        const int64_t p = W.cscpos ? (int64_t)W.cscpos[rl.x + q] : find_row(A.col_ptr, A.row_idx, mi, W.mc[j]);
+        if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[j]), k, mi, p);
+    }
+    if (__ballot(b.k != kNoPos)) reduce_best<64>(b);
+    if (l64 == 0) publish(A, W, j, b);
+}
+
+// Roots of one wave searched by the whole wave when they are this few;
+// more than that go to the wave-per-root kernel, which runs them in
+// parallel.  Only 4-lane tiles take them: on wider tiles the extra code
+// slowed the tile path itself by more than it saved (measured on the 27-point
+// stencil, whose roots all fit the tile).
+template <int T>
+constexpr int kWideMax = T == 4 ? 2 : 0;
+
+// Steps A-C of one group of 64 / T roots (a tile per root); see below.
 template <int T, int E>
-__global__ __launch_bounds__(256, 8) void k_search_filter(Csc A, Work W, int32_t long_threshold, int slot,
-                                                       const int32_t* __restrict__ roots, int32_t cap) {
-    if (round_over(W)) return;
-    const int lane = threadIdx.x & (T - 1);
-    const int64_t ntiles = roots ? W.counters[slot_word(slot, kRoots)] : A.n;
-    const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / T;
-    if (((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63)) / T >= ntiles) return;  // wave-uniform
-    const RootView r = load_root(W, t, ntiles, roots, long_threshold);
-    if (r.own && roots && lane == 0) W.dirty[r.j] = 0;
-    const bool handoff = r.slen > 0 && (r.slen > T * E || r.rl.y > T * E);
-    hand_off(W, slot, blockIdx.x & (kSpread - 1), cap, r.j, handoff && lane == 0);
-    const bool search = r.slen > 0 && !handoff;
+__device__ __forceinline__ void search_group(const Csc& A, const Work& W, const RootView& r, int slot, int sub,
+                                             int32_t cap, bool listed) {
+    const int l64 = threadIdx.x & 63;
+    const int lane = l64 & (T - 1);
+    if (r.own && listed && lane == 0) W.dirty[r.j] = 0;
+    // too long for the tile: the wave searches it when both lists fit 64
+    // lanes and the wave has at most kWideMax such roots, else the
+    // wave-per-root kernel does
+    const bool big = r.slen > 0 && (r.slen > T * E || r.rl.y > T * E);
+    uint64_t wm = __ballot(big && r.slen <= 64 && r.rl.y <= 64 && lane == 0);
+    if (__popcll(wm) > kWideMax<T>) wm = 0;  // wave-uniform
+    const bool wide = (wm >> l64) & 1u;
+    hand_off(W, slot, sub, cap, r.j, big && !wide && lane == 0);
+    const bool search = r.slen > 0 && !big;
     // loads, only as far as the wave's longest suffix and row list go:
     // indices clamped into the segment (the matched entry and the list's
     // first entry always exist), values past it masked
@@ -455,7 +488,23 @@ __global__ __launch_bounds__(256, 8) void k_search_filter(Csc A, Work W, int32_t
         }
     }
     if (__ballot(b.k != kNoPos)) reduce_best<T>(b);  // wave-uniform: most waves have no candidate
-    if (r.own && !handoff && lane == 0) publish(A, W, r.j, b);
+    if (r.own && !big && lane == 0) publish(A, W, r.j, b);
+    // the group's wide roots, one after the other
+    for (; wm; wm &= wm - 1)  // wave-uniform
+        search_wide(A, W, __builtin_amdgcn_readlane(r.j, __builtin_ctzll(wm)), l64);
+}
+
+// One group of 64 / T roots per wave.
+template <int T, int E>
+__global__ __launch_bounds__(256, 8) void k_search_filter(Csc A, Work W, int32_t long_threshold, int slot,
+                                                          const int32_t* __restrict__ roots, int32_t cap) {
+    constexpr int kTiles = 64 / T;
+    if (round_over(W)) return;
+    const int64_t ntiles = roots ? W.counters[slot_word(slot, kRoots)] : A.n;
+    const int64_t grp = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (grp * kTiles >= ntiles) return;  // wave-uniform
+    const RootView r = load_root(W, grp * kTiles + (threadIdx.x & 63) / T, ntiles, roots, long_threshold);
+    search_group<T, E>(A, W, r, slot, (int)(blockIdx.x & (kSpread - 1)), cap, roots != nullptr);
 }
 
 // ---------------------------------------------------------------------------

@@ -239,8 +239,11 @@ def serving_bench(args, dev, gen, gen_seconds, procs) -> dict:
     del plain_out
     print(f"[bench] plain back-to-back: {plain_rate:.1f} solves/s ({count} requests)", file=sys.stderr, flush=True)
 
+    # the stream already sits in page-locked buffers: the server reads them by
+    # reference (the plain path copies from the same buffers)
     srv_kw = dict(workers=args.serving_workers, max_batch=args.serving_max_batch,
-                  arena_bytes=args.serving_arena_gib << 30)
+                  arena_bytes=args.serving_arena_gib << 30, rounds_per_step=args.serving_rounds_per_step,
+                  copy_inputs=False)
 
     def served_run(m, arrivals, check=False):
         """Submit requests 0..m-1 at the arrival times (None: all at once);
@@ -301,7 +304,7 @@ def serving_bench(args, dev, gen, gen_seconds, procs) -> dict:
                "plain": {"solves_per_s": m / pspan, "p50_ms": _pct(pl, 50), "p99_ms": _pct(pl, 99)},
                "served": {"solves_per_s": m / sspan, "p50_ms": _pct(sl, 50), "p99_ms": _pct(sl, 99),
                           "batches": sst["batches"], "max_batch": sst["max_batch_seen"],
-                          "max_running": sst["max_running"]}}
+                          "max_running": sst["max_running"], "joined": sst["joined"]}}
         print(f"[bench] load {f} ({m} requests): plain p50/p99 {row['plain']['p50_ms']:.2f}/"
               f"{row['plain']['p99_ms']:.2f} ms, served p50/p99 {row['served']['p50_ms']:.2f}/"
               f"{row['served']['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
@@ -419,6 +422,8 @@ def main(argv=None) -> int:
     ap.add_argument("--serving-workers", type=int, default=4)
     ap.add_argument("--serving-max-batch", type=int, default=64)
     ap.add_argument("--serving-arena-gib", type=int, default=16)
+    ap.add_argument("--serving-rounds-per-step", type=int, default=8,
+                    help="rounds a server worker runs between admissions (0: a request's rounds in one step)")
     ap.add_argument("--serving-pinned", type=int, default=1,
                     help="1: the serving stream's host arrays are page-locked (both paths)")
     ap.add_argument("--serving-rates", type=lambda t: [float(x) for x in t.split(",")],

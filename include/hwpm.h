@@ -363,22 +363,30 @@ int hwpm_match_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, int32_t
 
 /* ---- serving --------------------------------------------------------------
  * A request loop for callers that produce a stream of independent matrices
- * (e.g. a sparse direct solver that pivots every matrix it factorises).
- * hwpm_submit queues a HOST CSC by reference.  Each worker owns a handle on
- * its own HIP stream: whenever it is idle it admits, in arrival order, as
- * many queued requests as fit into the largest free extent of the server's
- * device arena (their inputs, results and the batch workspace -- admission by
- * HBM footprint), copies them in, validates and solves them as one
- * hwpm_match_batch and hands back the results.  Requests that arrive while
- * batches run join the next batch that has room (continuous batching), and
- * the batches of different workers overlap on the device.  Results equal
- * those of hwpm_match on each matrix alone.
+ * (e.g. a sparse direct solver that pivots every matrix it factorises), with
+ * continuous batching at round granularity.  Each worker owns a handle on its
+ * own HIP stream and the requests it holds in flight; it works in steps.  In
+ * each step it admits, in arrival order, as many queued requests as fit the
+ * server's device arena (each request's inputs and matching stay in a region
+ * of the arena while it is in flight; the batch workspace is sized to all of
+ * the worker's requests -- admission by HBM footprint), finds their perfect
+ * matchings, and then runs up to rounds_per_step weight-improvement rounds
+ * (Section 5.3) on every request it holds, old and new, as one block-diagonal
+ * batch.  Requests whose rounds have ended leave with their results; the
+ * others stay resident and continue in the next step, together with the
+ * requests that arrived meanwhile.  The workers' steps overlap on the
+ * device.  Every result (permutation, total, round count, cycles) equals
+ * that of hwpm_match on the matrix alone: a round depends on the matching
+ * alone, whichever call runs it.
  *
- * Ownership: the caller's host arrays of a request must stay valid and
- * unchanged until hwpm_poll has returned its result (or until
- * hwpm_server_destroy has returned).  The server allocates its arena
- * (arena_bytes of device memory) and one stream and handle per worker;
- * hwpm_server_destroy finishes the queued requests and frees everything.
+ * Ownership: with copy_inputs = 1 (default) hwpm_submit copies the host
+ * arrays and the caller may reuse them at once; with copy_inputs = 0 they are
+ * kept by reference and must stay valid and unchanged until hwpm_poll has
+ * returned the result (or until hwpm_server_destroy has returned) -- the
+ * cheaper form when the arrays already sit in page-locked memory.  The
+ * server allocates its arena (arena_bytes of device memory) and one stream
+ * and handle per worker; hwpm_server_destroy finishes the queued requests and
+ * frees everything.
  *
  * Threads: hwpm_submit, hwpm_poll and hwpm_server_get_stats are
  * thread-safe.  A ticket belongs to the first hwpm_poll that waits for it or
@@ -400,33 +408,41 @@ typedef struct {
      * solve.probe / solve.tile_width as given. */
     int32_t tune;
     size_t arena_bytes;      /* device memory the server owns, >= 1 MiB */
-    hwpm_options solve;      /* options of every hwpm_match_batch call */
+    hwpm_options solve;      /* solve options of every request (solve.max_rounds caps each
+                              * request's own rounds, over all its steps) */
+    int32_t rounds_per_step; /* rounds a worker runs between admissions, >= 0 (default 8;
+                              * 0 = a request's rounds all run in its first step) */
+    int32_t copy_inputs;     /* 1 (default): hwpm_submit copies the host arrays; 0: by reference */
 } hwpm_server_options;
 
 typedef struct {
     hwpm_item_stats item;    /* the request's statistics (item.status = its status) */
     double queue_ms;         /* host clock: submit -> admitted into a batch */
     double latency_ms;       /* host clock: submit -> result ready */
-    int32_t batch_size;      /* requests in the batch that solved it */
+    int32_t batch_size;      /* requests in the step that admitted it */
     int32_t worker;          /* worker that solved it */
+    int32_t steps;           /* round steps it took part in */
+    int32_t reserved;
 } hwpm_request_info;
 
 typedef struct {
     int64_t submitted;       /* requests accepted by hwpm_submit */
     int64_t completed;       /* requests with a result (any status) */
-    int64_t batches;         /* batches launched */
-    int64_t max_batch_seen;  /* largest batch */
-    int64_t max_running;     /* most batches in flight at once */
+    int64_t batches;         /* steps run (each: admissions, matchings, one packed round batch) */
+    int64_t max_batch_seen;  /* most requests in one step */
+    int64_t max_running;     /* most steps in flight at once */
     int64_t pending;         /* requests waiting now */
-    int64_t running;         /* batches in flight now */
+    int64_t running;         /* steps in flight now */
     int64_t arena_in_use;    /* arena bytes held now */
     int64_t arena_peak;      /* most arena bytes held at once */
+    int64_t joined;          /* requests admitted into a step next to requests already in flight */
 } hwpm_server_stats;
 
-/* Defaults: device 0, 2 workers, max_batch 64, 8 GiB arena, solve options
- * from hwpm_default_options (check_csc = 1: every batch is validated on the
- * device; a batch with a malformed member is solved member by member, so
- * only that member reports HWPM_EBADCSC). */
+/* Defaults: device 0, 2 workers, max_batch 64, 8 GiB arena, 8 rounds per
+ * step, inputs copied at submission, solve options from hwpm_default_options
+ * (check_csc = 1: every request is validated on the device when admitted; a
+ * step whose fresh requests include a malformed one matches them one by one,
+ * so only that one reports HWPM_EBADCSC). */
 void hwpm_server_default_options(hwpm_server_options* opt);
 
 /* Start a server (opt may be NULL for the defaults).  Errors: HWPM_EINVAL
@@ -437,8 +453,8 @@ int hwpm_server_create(hwpm_server* out, const hwpm_server_options* opt);
  * not yet polled are discarded. */
 int hwpm_server_destroy(hwpm_server s);
 
-/* Queue one matrix; A holds HOST pointers, kept by reference (see
- * ownership above).  *ticket identifies the request in hwpm_poll.  Errors:
+/* Queue one matrix; A holds HOST pointers, copied or kept by reference as
+ * copy_inputs says (see ownership above).  *ticket identifies the request in hwpm_poll.  Errors:
  * HWPM_EINVAL (null pointer, negative size), HWPM_ETOOBIG, HWPM_EBADCSC
  * (col_ptr[0] != 0 or col_ptr[n] != nnz); a rejected matrix is not queued.
  * Every other check of hwpm_check_csc runs on the device and its failure is

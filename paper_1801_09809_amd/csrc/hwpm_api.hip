@@ -9,6 +9,7 @@
 
 #include "hwpm.h"
 #include "hwpm_internal.h"
+#include "hwpm_serving.h"
 
 using namespace hwpm;
 
@@ -843,10 +844,13 @@ int hwpm_batch_workspace_bytes(int32_t count, const hwpm_csc* mats, size_t* byte
     return HWPM_OK;
 }
 
+// match: find the perfect matchings first (hwpm_match_batch); phase1_only:
+// stop there, with every block's matching in its perm_out (blocks without
+// one: status HWPM_ESINGULAR, perm_out untouched).
 static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const int32_t* const* mate_in,
                      int32_t* const* perm_out, double* totals, const hwpm_options* opt_in,
                      hwpm_item_stats* items, hwpm_stats* stats, void* workspace, size_t workspace_bytes,
-                     bool match) {
+                     bool match, bool phase1_only) {
     const auto t_begin = std::chrono::steady_clock::now();
     if (!h || count < 0 || (count > 0 && (!mats || !perm_out))) return HWPM_EINVAL;
     if (!match && count > 0 && !mate_in) return HWPM_EINVAL;
@@ -910,44 +914,69 @@ static int run_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const i
     const int32_t* start = P.mate;
     if (match) {
         st = run_initial_matching(h, A, W, M, opt.mcm_plain ? 0 : 1, opt.timing == 1, opt.graph != 0, &S);
-        if (st == HWPM_ESINGULAR) {
-            // some blocks have no perfect matching: solve the others one by one
-            std::vector<int32_t> unm(count);
-            HIP_TRY(launch_item_unmatched(P, M.mc, h->stream, h->cus));
-            HIP_TRY(hipMemcpyAsync(unm.data(), P.item_unmatched, (size_t)count * 4, hipMemcpyDeviceToHost,
-                                   h->stream));
+        if (st != HWPM_OK && st != HWPM_ESINGULAR) return st;
+        if (st == HWPM_ESINGULAR || phase1_only) {
+            // Blocks without a perfect matching are masked out: the others'
+            // matchings are unpacked and improved as a smaller packed batch
+            // (no block joins another, so each still gets its result alone).
+            const bool singular = st == HWPM_ESINGULAR;
+            std::vector<int32_t> unm(count, 0);
+            if (singular) {
+                HIP_TRY(launch_item_unmatched(P, M.mc, h->stream, h->cus));
+                HIP_TRY(hipMemcpyAsync(unm.data(), P.item_unmatched, (size_t)count * 4, hipMemcpyDeviceToHost,
+                                       h->stream));
+            }
+            HIP_TRY(launch_unpack(P, M.mc, h->stream, h->cus, singular ? P.item_unmatched : nullptr));
             HIP_TRY(hipStreamSynchronize(h->stream));
+            std::vector<int32_t> keep;
             for (int32_t b = 0; b < count; ++b) {
-                if (unm[b] > 0) {
-                    if (items) {
-                        memset(&items[b], 0, sizeof(hwpm_item_stats));
-                        items[b].status = HWPM_ESINGULAR;
-                    }
-                    continue;
-                }
-                hwpm_stats Sb;
-                double tb = 0.0;
-                hwpm_options ob = opt;
-                ob.check_csc = 0;
-                const int sb = hwpm_match(h, &mats[b], perm_out[b], &tb, &ob, &Sb, rest,
-                                          workspace_bytes - head);
-                if (sb != HWPM_OK) return sb;
-                if (totals) totals[b] = tb;
                 if (items) {
-                    items[b].status = HWPM_OK;
-                    items[b].rounds = Sb.rounds;
-                    items[b].hit_round_cap = Sb.hit_round_cap;
-                    items[b].reserved = 0;
-                    items[b].cycles_applied = Sb.cycles_applied;
-                    items[b].init_weight = Sb.init_weight;
-                    items[b].final_weight = Sb.final_weight;
+                    memset(&items[b], 0, sizeof(hwpm_item_stats));
+                    items[b].status = unm[b] > 0 ? HWPM_ESINGULAR : HWPM_OK;
                 }
+                if (totals) totals[b] = 0.0;
+                if (unm[b] == 0) keep.push_back(b);
+            }
+            if (!phase1_only && !keep.empty()) {
+                const size_t k = keep.size();
+                std::vector<hwpm_csc> km(k);
+                std::vector<const int32_t*> kin(k);
+                std::vector<int32_t*> kout(k);
+                std::vector<double> kt(k);
+                std::vector<hwpm_item_stats> ki(k);
+                for (size_t q = 0; q < k; ++q) {
+                    km[q] = mats[keep[q]];
+                    kin[q] = perm_out[keep[q]];
+                    kout[q] = perm_out[keep[q]];
+                }
+                hwpm_options ok = opt;
+                ok.check_csc = 0;  // validated above
+                hwpm_stats Sk;
+                st = run_batch(h, (int32_t)k, km.data(), kin.data(), kout.data(), kt.data(), &ok, ki.data(), &Sk,
+                               workspace, workspace_bytes, false, false);
+                if (st != HWPM_OK) return st;
+                for (size_t q = 0; q < k; ++q) {
+                    if (totals) totals[keep[q]] = kt[q];
+                    if (items) items[keep[q]] = ki[q];
+                }
+                // the rounds' statistics are the smaller batch's; the initial
+                // matching's stay this call's
+                hwpm_stats P1 = S;
+                S = Sk;
+                S.greedy_rounds = P1.greedy_rounds;
+                S.greedy_cardinality = P1.greedy_cardinality;
+                S.mcm_cardinality = P1.mcm_cardinality;
+                S.mcm_phases = P1.mcm_phases;
+                S.mcm_levels = P1.mcm_levels;
+                S.ms_check = P1.ms_check;
+                S.ms_greedy = P1.ms_greedy;
+                S.ms_mcm = P1.ms_mcm;
+                S.graph_launches += P1.graph_launches;
             }
             S.ms_total = std::chrono::duration<float, std::milli>(std::chrono::steady_clock::now() - t_begin).count();
             if (stats) *stats = S;
             return HWPM_OK;
         }
-        if (st != HWPM_OK) return st;
         start = M.mc;
     }
     double total = 0.0;
@@ -1051,15 +1080,26 @@ int hwpm_improve_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, const
                        hwpm_item_stats* items, hwpm_stats* stats, void* workspace,
                        size_t workspace_bytes) {
     return run_batch(h, count, mats, mate_in, perm_out, totals, opt, items, stats, workspace,
-                     workspace_bytes, false);
+                     workspace_bytes, false, false);
 }
 
 int hwpm_match_batch(hwpm_handle h, int32_t count, const hwpm_csc* mats, int32_t* const* perm_out,
                      double* totals, const hwpm_options* opt, hwpm_item_stats* items,
                      hwpm_stats* stats, void* workspace, size_t workspace_bytes) {
     return run_batch(h, count, mats, nullptr, perm_out, totals, opt, items, stats, workspace,
-                     workspace_bytes, true);
+                     workspace_bytes, true, false);
 }
 
 
 }  // extern "C"
+
+namespace hwpm {
+
+int match_batch_initial(hwpm_handle h, int32_t count, const hwpm_csc* mats, int32_t* const* perm_out,
+                        const hwpm_options* opt, hwpm_item_stats* items, void* workspace,
+                        size_t workspace_bytes) {
+    return run_batch(h, count, mats, nullptr, perm_out, nullptr, opt, items, nullptr, workspace,
+                     workspace_bytes, true, true);
+}
+
+}  // namespace hwpm

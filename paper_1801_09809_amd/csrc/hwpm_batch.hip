@@ -69,12 +69,15 @@ __global__ __launch_bounds__(256) void k_pack_entries(const BatchItem* __restric
     }
 }
 
+// skip (nullable): blocks with skip[b] != 0 keep their perm_out untouched.
 __global__ __launch_bounds__(256) void k_unpack_perm(const BatchItem* __restrict__ items,
                                                      const int32_t* __restrict__ chunk_item,
                                                      const int64_t* __restrict__ chunk_first,
-                                                     const int32_t* __restrict__ mc, int32_t nchunks) {
+                                                     const int32_t* __restrict__ mc, int32_t nchunks,
+                                                     const int32_t* __restrict__ skip) {
     for (int32_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const int32_t b = chunk_item[c];
+        if (skip && skip[b] != 0) continue;  // block-uniform
         const BatchItem it = items[b];
         const int64_t j0 = chunk_first[c];
         const int64_t j1 = (j0 + kPackChunk < it.n) ? j0 + kPackChunk : it.n;
@@ -173,9 +176,9 @@ hipError_t launch_pack(const BatchPlan& P, bool with_mates, hipStream_t s, int c
     return hipGetLastError();
 }
 
-hipError_t launch_unpack(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus) {
+hipError_t launch_unpack(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus, const int32_t* skip) {
     hipLaunchKernelGGL(k_unpack_perm, dim3(cus * 8), dim3(256), 0, s, P.items, P.col_chunk_item,
-                       P.col_chunk_first, mc, P.ncol_chunks);
+                       P.col_chunk_first, mc, P.ncol_chunks, skip);
     return hipGetLastError();
 }
 

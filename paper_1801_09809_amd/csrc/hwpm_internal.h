@@ -244,7 +244,9 @@ hipError_t launch_bfs_roots(const Csc& A, const Mcm& M, hipStream_t s, int cus);
 hipError_t launch_bfs_level(const Csc& A, const Mcm& M, int level, int heavy, hipStream_t s, int cus);
 hipError_t launch_bfs_augment(const Csc& A, const Mcm& M, hipStream_t s, int cus);
 hipError_t launch_pack(const BatchPlan& P, bool with_mates, hipStream_t s, int cus);
-hipError_t launch_unpack(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus);
+// skip (nullable): blocks with skip[b] != 0 keep their perm_out untouched.
+hipError_t launch_unpack(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus,
+                         const int32_t* skip = nullptr);
 hipError_t launch_seg_tree(const BatchPlan& P, const double* x, double* out, hipStream_t s, int cus);
 hipError_t launch_item_rounds(const BatchPlan& P, const int32_t* done, hipStream_t s);
 hipError_t launch_item_unmatched(const BatchPlan& P, const int32_t* mc, hipStream_t s, int cus);

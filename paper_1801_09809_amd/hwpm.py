@@ -155,6 +155,8 @@ class hwpm_server_options(ctypes.Structure):
         ("tune", ctypes.c_int32),
         ("arena_bytes", ctypes.c_size_t),
         ("solve", hwpm_options),
+        ("rounds_per_step", ctypes.c_int32),
+        ("copy_inputs", ctypes.c_int32),
     ]
 
 
@@ -165,19 +167,21 @@ class hwpm_request_info(ctypes.Structure):
         ("latency_ms", ctypes.c_double),
         ("batch_size", ctypes.c_int32),
         ("worker", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self) -> dict:
         d = self.item.as_dict()
         d.update(queue_ms=self.queue_ms, latency_ms=self.latency_ms, batch_size=self.batch_size,
-                 worker=self.worker)
+                 worker=self.worker, steps=self.steps)
         return d
 
 
 class hwpm_server_stats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "submitted", "completed", "batches", "max_batch_seen", "max_running", "pending", "running",
-        "arena_in_use", "arena_peak")]
+        "arena_in_use", "arena_peak", "joined")]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -692,11 +696,13 @@ class Solver:
 
 
 class Server:
-    """Request loop over host matrices (numpy arrays): submit, then poll.  The
-    arrays of a request are kept alive here until its result is polled."""
+    """Request loop over host matrices (numpy arrays): submit, then poll.  With
+    copy_inputs=False the server reads the caller's arrays until the result is
+    polled, and they are kept alive here until then."""
 
     def __init__(self, device: int = 0, workers: int = 2, max_batch: int = 64,
-                 arena_bytes: int = 8 << 30, tune: bool = True, **solve_kw):
+                 arena_bytes: int = 8 << 30, tune: bool = True, rounds_per_step: int = 8,
+                 copy_inputs: bool = True, **solve_kw):
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible: the HWPM library runs on the device only")
         opt = hwpm_server_default_options()
@@ -705,11 +711,14 @@ class Server:
         opt.max_batch = int(max_batch)
         opt.arena_bytes = int(arena_bytes)
         opt.tune = int(bool(tune))
+        opt.rounds_per_step = int(rounds_per_step)
+        opt.copy_inputs = int(bool(copy_inputs))
         if solve_kw:
             opt.solve = Solver.options(**solve_kw)
         self.server = hwpm_server_create(opt)
+        self._copy = bool(copy_inputs)
         self._n = {}
-        self._keep = {}  # the host arrays of each queued request, until polled
+        self._keep = {}  # the host arrays of each queued request, until polled (by reference only)
 
     def close(self):
         if self.server:
@@ -741,7 +750,8 @@ class Server:
         if st != HWPM_OK:
             raise HwpmError(st, "hwpm_submit")
         self._n[ticket] = n
-        self._keep[ticket] = (cp, ri, ww)  # the server reads them until the result is polled
+        if not self._copy:
+            self._keep[ticket] = (cp, ri, ww)  # the server reads them until the result is polled
         return ticket
 
     def poll(self, ticket: int, wait: bool = True):

@@ -75,7 +75,8 @@ def test_served_equals_oracle(workers, max_batch):
     assert stats["max_batch_seen"] <= max_batch
     assert 0 < stats["arena_peak"] <= 256 << 20
     if max_batch == 1:
-        assert stats["batches"] == len(wls)
+        # one request per step; a request whose rounds outlast a step takes more
+        assert stats["batches"] >= len(wls) and stats["joined"] == 0
 
 
 def test_continuous_batching_admits_waiting_requests():
@@ -93,6 +94,70 @@ def test_continuous_batching_admits_waiting_requests():
         _check(wl, res)
     assert stats["batches"] < 1 + len(small)
     assert stats["max_batch_seen"] > 1
+
+
+def test_requests_join_rounds_in_flight():
+    """With one worker and one round per step, requests that arrive while a
+    request's rounds run join its next round batch (packed with it); every
+    result -- permutation, total, round and cycle counts -- still equals the
+    oracle's for the matrix alone, and the long request took one step per
+    round."""
+    hwpm = _need_gpu()
+    big = stencil27(24, 24, 24, 35, 45, name="stencil_24cubed")
+    ref_big = oracle_match(big.n, big.col_ptr, big.row_idx, big.w)
+    assert ref_big.rounds >= 3
+    small = _requests(17, 16)
+    print(f"[gpu] joining: {big.name} ({ref_big.rounds} rounds) + {len(small)} requests", flush=True)
+    with hwpm.Server(workers=1, max_batch=64, arena_bytes=1 << 30, rounds_per_step=1) as srv:
+        t0 = srv.submit(big.col_ptr, big.row_idx, big.w)
+        deadline = time.time() + 60
+        while srv.stats()["running"] == 0 and time.time() < deadline:
+            time.sleep(0.0002)
+        ts = [srv.submit(w.col_ptr, w.row_idx, w.w) for w in small]
+        results = [srv.poll(t) for t in [t0] + ts]
+        stats = srv.stats()
+    for wl, res in zip([big] + small, results):
+        _check(wl, res)
+    assert results[0][3]["steps"] == ref_big.rounds
+    assert stats["joined"] > 0
+    assert stats["pending"] == 0 and stats["running"] == 0 and stats["arena_in_use"] == 0
+
+
+@pytest.mark.parametrize("cap", [1, 2, 3])
+def test_round_cap_over_steps(cap):
+    """solve.max_rounds caps each request's own rounds over all its steps:
+    rounds, hit_round_cap and the result equal the oracle's with that cap."""
+    hwpm = _need_gpu()
+    wls = [stencil27(16, 16, 16, 3, 4, name="stencil_16cubed"), small_random(3000, 6, 12),
+           rmat(10, 16, 1010, 2010, 3010, name="rmat_s10"), small_random(0, 1, 1)]
+    with hwpm.Server(workers=1, max_batch=64, arena_bytes=256 << 20, rounds_per_step=2, max_rounds=cap) as srv:
+        results = [srv.poll(t) for t in [srv.submit(w.col_ptr, w.row_idx, w.w) for w in wls]]
+    for wl, (st, perm, total, info) in zip(wls, results):
+        ref = oracle_match(wl.n, wl.col_ptr, wl.row_idx, wl.w, max_rounds=cap)
+        assert st == 0 and ref.status == 0, wl.name
+        assert np.array_equal(perm[:wl.n], ref.perm), wl.name
+        assert np.float64(total).tobytes() == np.float64(ref.total).tobytes(), wl.name
+        assert (info["rounds"], bool(info["hit_round_cap"]), info["cycles_applied"]) == \
+            (ref.rounds, bool(ref.hit_round_cap), ref.cycles_applied), wl.name
+        assert np.float64(info["init_weight"]).tobytes() == np.float64(ref.init_weight).tobytes(), wl.name
+
+
+def test_submit_copies_inputs():
+    """By default hwpm_submit copies the host arrays: the caller may overwrite
+    them at once; with copy_inputs off they are read later (and kept alive by
+    the binding until polled)."""
+    hwpm = _need_gpu()
+    wl = small_random(2000, 5, 77)
+    for copy in (True, False):
+        with hwpm.Server(workers=1, copy_inputs=copy) as srv:
+            cp, ri, w = wl.col_ptr.copy(), wl.row_idx.copy(), wl.w.copy()
+            t = srv.submit(cp, ri, w)
+            if copy:
+                cp[1:] = 0
+                ri[:] = 0
+                w[:] = np.nan
+            res = srv.poll(t)
+        _check(wl, res)
 
 
 def test_admission_by_footprint():

@@ -558,10 +558,21 @@ __device__ __forceinline__ int32_t wave_incl_max(int32_t v) {
     return v;
 }
 
+// Packed entries: when a slot's offset inside its bucket (rb bits) and a
+// column fit one 32-bit word together (n <= 2^(32 - rb)), passes 1b-3 move
+// that word instead of two, the column in the low 32 - rb bits.
+__device__ __forceinline__ int32_t tp_pack(int32_t slot, int32_t col, int rb) {
+    return (int32_t)(((uint32_t)slot & ((1u << rb) - 1u)) << (32 - rb) | (uint32_t)col);
+}
+__device__ __forceinline__ int32_t tp_local(int32_t word, int rb) { return (int32_t)((uint32_t)word >> (32 - rb)); }
+__device__ __forceinline__ int32_t tp_col_of(int32_t word, int rb) {
+    return (int32_t)((uint32_t)word & ((1u << (32 - rb)) - 1u));
+}
+
 // Pass 1b: sort the tile by bucket in LDS, write the triples in runs.  NT
 // threads per block; MB bounds the bucket count (the LDS tables are sized by
 // it, so the small form leaves room for more blocks per CU).
-template <bool POS, int NT, int MB>
+template <bool POS, int NT, int MB, bool PACK>
 __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
                                                    const int64_t* __restrict__ off) {
     constexpr int U = kTpTile / NT, NW = NT / 64;
@@ -654,8 +665,12 @@ __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_
         const int32_t slot = s_slot[e];
         const int32_t b = slot >> rb;
         const int32_t g = base[b] + (e - start[b]);
-        W.tp_row[g] = slot;
-        W.tp_col[g] = s_col[e];
+        if (PACK) {
+            W.tp_row[g] = tp_pack(slot, s_col[e], rb);
+        } else {
+            W.tp_row[g] = slot;
+            W.tp_col[g] = s_col[e];
+        }
         if (POS) W.tp_pos[g] = s_pos[e];
     }
 }
@@ -665,10 +680,10 @@ __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_
 // leave in runs, and records where each sub-bucket starts.
 constexpr int kTpSub = 64;
 
-template <bool POS>
+template <bool POS, bool PACK>
 __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
                                                    const int64_t* __restrict__ off) {
-    __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
+    __shared__ int32_t s_slot[kTpTile], s_col[PACK ? 1 : kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[kTpSub], start[kTpSub], cursor[kTpSub];
     const int32_t b = blockIdx.x;
     const int64_t r0 = (int64_t)b << rb;
@@ -689,7 +704,8 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u)
-            if (eb + t + (int64_t)blockDim.x * u < e1) atomicAdd(&hist[(v[u] - r0) >> sb], 1);
+            if (eb + t + (int64_t)blockDim.x * u < e1)
+                atomicAdd(&hist[(PACK ? tp_local(v[u], rb) : v[u] - (int32_t)r0) >> sb], 1);
     }
     __syncthreads();
     if (t < 64) {  // one wave scans the 64 sub-bucket counts
@@ -715,16 +731,14 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
             const int32_t x = t + 1024 * u;
             const int64_t xc = t0 + (x < len ? x : len - 1);
             sl[u] = W.tp_row[xc];
-            co[u] = W.tp_col[xc];
+            co[u] = PACK ? 0 : W.tp_col[xc];
             ps[u] = POS ? W.tp_pos[xc] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            if (t + 1024 * u < len)
-                rk[u] = atomicAdd(&hist[(sl[u] - r0) >> sb], 1);
-            else
-                sl[u] = -1;
-        }
+        for (int u = 0; u < 4; ++u)  // rank -1: past the tile
+            rk[u] = (t + 1024 * u < len)
+                        ? atomicAdd(&hist[(PACK ? tp_local(sl[u], rb) : sl[u] - (int32_t)r0) >> sb], 1)
+                        : -1;
         __syncthreads();
         if (t < 64) {
             const int32_t v = hist[t];
@@ -739,19 +753,19 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            if (sl[u] >= 0) {
-                const int32_t x = start[(sl[u] - r0) >> sb] + rk[u];
+            if (rk[u] >= 0) {
+                const int32_t x = start[(PACK ? tp_local(sl[u], rb) : sl[u] - (int32_t)r0) >> sb] + rk[u];
                 s_slot[x] = sl[u];
-                s_col[x] = co[u];
+                if (!PACK) s_col[x] = co[u];
                 if (POS) s_pos[x] = ps[u];
             }
         }
         __syncthreads();
         for (int32_t x = t; x < len; x += blockDim.x) {
-            const int32_t g = (s_slot[x] - (int32_t)r0) >> sb;
+            const int32_t g = (PACK ? tp_local(s_slot[x], rb) : s_slot[x] - (int32_t)r0) >> sb;
             const int64_t q = e0 + cursor[g] + (x - start[g]);
             W.tp_row2[q] = s_slot[x];
-            W.tp_col2[q] = s_col[x];
+            if (!PACK) W.tp_col2[q] = s_col[x];
             if (POS) W.tp_pos2[q] = s_pos[x];
         }
         __syncthreads();
@@ -767,7 +781,7 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
 // and written as one run per slot.
 constexpr int kPlaceTile = 2048;  // entries per LDS tile (256 threads x 8)
 
-template <bool POS>
+template <bool POS, bool PACK>
 __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t nb) {
     constexpr int NS = kTpMaxRows / kTpSub;  // slots per sub-bucket, at most 128
     constexpr int U = kPlaceTile / 256;
@@ -794,9 +808,10 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
         for (int u = 0; u < U; ++u) {
             const int64_t x = c0 + t + 256 * u;
             const int64_t xc = e0 + (x < len ? x : len - 1);
-            key[u] = (int32_t)(W.tp_row2[xc] - s0);
+            const int32_t wd = W.tp_row2[xc];
+            key[u] = PACK ? (tp_local(wd, rb) & ((1 << sb) - 1)) : (int32_t)(wd - s0);
             if (one_tile) {
-                col[u] = W.tp_col2[xc];
+                col[u] = PACK ? tp_col_of(wd, rb) : W.tp_col2[xc];
                 pos[u] = POS ? W.tp_pos2[xc] : 0;
             }
         }
@@ -851,8 +866,9 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
         for (int u = 0; u < U; ++u) {  // loads first, indices clamped into the tile
             const int32_t x = t + 256 * u;
             const int64_t xc = e0 + c0 + (x < tl ? x : tl - 1);
-            key[u] = (int32_t)(W.tp_row2[xc] - s0);
-            col[u] = W.tp_col2[xc];
+            const int32_t wd = W.tp_row2[xc];
+            key[u] = PACK ? (tp_local(wd, rb) & ((1 << sb) - 1)) : (int32_t)(wd - s0);
+            col[u] = PACK ? tp_col_of(wd, rb) : W.tp_col2[xc];
             pos[u] = POS ? W.tp_pos2[xc] : 0;
         }
 #pragma unroll
@@ -884,6 +900,20 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     }
 }
 
+// Passes 1b-3 (scatter, split, place) in one of their forms.
+template <bool POS, bool PACK>
+void launch_tp_sort(const Csc& A, const Work& W, const TpPlan& P, hipStream_t s) {
+    const int32_t nb = (int32_t)P.nb, nseg = (int32_t)P.nseg;
+    constexpr int NT = kTpScatterThreads;
+    if (nb <= 256)
+        hipLaunchKernelGGL((k_tp_scatter<POS, NT, 256, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+    else
+        hipLaunchKernelGGL((k_tp_scatter<POS, NT, kTpMaxBuckets, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, nseg,
+                           W.tp_off);
+    hipLaunchKernelGGL((k_tp_split<POS, PACK>), dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+    hipLaunchKernelGGL((k_tp_place<POS, PACK>), dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
+}
+
 hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions, hipStream_t s, int cus) {
     const TpPlan P = tp_plan(A.n, A.nnz);
     const int32_t nb = (int32_t)P.nb, nseg = (int32_t)P.nseg;
@@ -894,20 +924,14 @@ hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions,
     hipLaunchKernelGGL(k_scan_local, dim3((unsigned)sb), dim3(256), 0, s, W.tp_cnt, m, W.tp_off, W.tp_sums);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, W.tp_sums, sb, W.tp_off + m);
     hipLaunchKernelGGL(k_scan_add, dim3(cus * 8), dim3(256), 0, s, W.tp_off, m, W.tp_sums);
+    // a slot's offset in its bucket and a column share one word when they fit
+    const bool pack = (int64_t)A.n <= ((int64_t)1 << (32 - P.rb));
     if (positions) {
-        if (nb <= 256)
-            hipLaunchKernelGGL((k_tp_scatter<true, kTpScatterThreads, 256>), dim3(nseg), dim3(kTpScatterThreads), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-        else
-            hipLaunchKernelGGL((k_tp_scatter<true, kTpScatterThreads, kTpMaxBuckets>), dim3(nseg), dim3(kTpScatterThreads), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-        hipLaunchKernelGGL(k_tp_split<true>, dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-        hipLaunchKernelGGL(k_tp_place<true>, dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
+        if (pack) launch_tp_sort<true, true>(A, W, P, s);
+        else launch_tp_sort<true, false>(A, W, P, s);
     } else {
-        if (nb <= 256)
-            hipLaunchKernelGGL((k_tp_scatter<false, kTpScatterThreads, 256>), dim3(nseg), dim3(kTpScatterThreads), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-        else
-            hipLaunchKernelGGL((k_tp_scatter<false, kTpScatterThreads, kTpMaxBuckets>), dim3(nseg), dim3(kTpScatterThreads), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-        hipLaunchKernelGGL(k_tp_split<false>, dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
-        hipLaunchKernelGGL(k_tp_place<false>, dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
+        if (pack) launch_tp_sort<false, true>(A, W, P, s);
+        else launch_tp_sort<false, false>(A, W, P, s);
     }
     return hipGetLastError();
 }

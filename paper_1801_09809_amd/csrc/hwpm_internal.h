@@ -8,7 +8,7 @@ namespace hwpm {
 
 constexpr int32_t kNoRoot = 0x7fffffff;   // empty Step-D slot
 constexpr int kSlots = 8;                  // ring of per-round counter pairs
-constexpr int kLongChunk = 1024;           // entries per block in the long-column search
+constexpr int kLongChunk = 2048;           // entries per block in the long-column search
 constexpr int kTreeBlock = 2048;           // leaves summed by one tree-sum block
 constexpr int kMaxRoundStats = 512;        // rounds with per-round statistics
 

@@ -3,7 +3,7 @@
 // the gain of the alternating 4-cycle and the per-root winner.
 //
 // Roots are binned by size: a tile of lanes per short root, a wave per
-// medium root, a block per 1024-entry chunk of a long column.  The closing
+// medium root, a block per 2048-entry chunk of a long column.  The closing
 // edge is probed by binary search of column m_i (probe 1) or, the GPU form of
 // the marking trick of Section 4, by testing m_i against the row list of m_j
 // from the matching-ordered transpose (probes 2-5).  Every probe gives the

@@ -125,8 +125,9 @@ struct Work {
     int32_t* tp_row;
     int32_t* tp_col;
     int32_t* tp_pos;
-    int32_t* tp_cnt;    // bucket-major (bucket, segment) counts
-    int64_t* tp_off;    // their exclusive scan (+ total)
+    int32_t* tp_cnt;    // tile-major (tile, bucket) counts, then their scan inside each part of tiles
+    int64_t* tp_off;    // per (part of tiles, bucket): where its entries of that bucket begin
+    int64_t* tp_bstart; // bucket starts (+ nnz)
     int64_t* tp_sums;
     int32_t* tp_row2;   // pass-2 output, grouped by sub-bucket
     int32_t* tp_col2;

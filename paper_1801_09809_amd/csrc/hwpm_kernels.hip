@@ -505,8 +505,8 @@ __device__ __forceinline__ void wave_scan128(int32_t* cnt) {
 }
 
 // Pass 1a: the slot of every entry (mrk[k] = m_i of its row, the mate
-// column the search streams) and the per-(bucket, tile) counts, written
-// bucket-major.
+// column the search streams) and the per-(tile, bucket) counts, one row of
+// nb counts per tile.
 __global__ __launch_bounds__(256) void k_tp_hist(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
                                                  int32_t* __restrict__ cnt) {
     constexpr int U = kTpTile / 256;
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(256) void k_tp_hist(Csc A, Work W, int rb, int32_t 
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[(int64_t)b * nseg + seg] = hist[b];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) cnt[(int64_t)seg * nb + b] = hist[b];
 }
 
 // Inclusive running maximum over the 64 lanes of a wave (values >= -1)
@@ -556,6 +556,79 @@ __device__ __forceinline__ int32_t wave_incl_max(int32_t v) {
     v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
     v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
     return v;
+}
+
+// The entries of (tile, bucket) go after those of every earlier bucket and,
+// in the same bucket, of every earlier tile: a scan down each column of the
+// tile-major count table.  Part 1: block q takes tiles [q S, q S + S) and,
+// per bucket, replaces each count by the sum of the counts above it inside
+// the part, and writes the part's sums.
+__global__ __launch_bounds__(256) void k_tp_colsum(int32_t* __restrict__ cnt, int32_t nb, int32_t nseg,
+                                                   int32_t S, int64_t* __restrict__ part) {
+    const int32_t s0 = blockIdx.x * S, s1 = (s0 + S < nseg) ? s0 + S : nseg;
+    for (int32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+        int32_t run = 0, s = s0;
+        for (; s + 8 <= s1; s += 8) {  // eight loads in flight, then the running sum
+            int32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = cnt[(int64_t)(s + u) * nb + b];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                cnt[(int64_t)(s + u) * nb + b] = run;
+                run += v[u];
+            }
+        }
+        for (; s < s1; ++s) {
+            const int32_t v = cnt[(int64_t)s * nb + b];
+            cnt[(int64_t)s * nb + b] = run;
+            run += v;
+        }
+        part[(int64_t)blockIdx.x * nb + b] = run;
+    }
+}
+
+// Part 2, one block, one bucket per thread (nb <= 1024): the parts' sums of
+// each bucket scanned down the parts, the bucket totals scanned across the
+// buckets (bstart, with bstart[nb] = nnz), and each part's value turned into
+// the global position where its entries of that bucket begin.
+__global__ __launch_bounds__(1024) void k_tp_colscan(int64_t* __restrict__ part, int32_t nb, int32_t nparts,
+                                                     int64_t* __restrict__ bstart, int64_t nnz) {
+    __shared__ int64_t wsum[16];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    int64_t run = 0;
+    if (t < nb) {
+        int32_t q = 0;
+        for (; q + 8 <= nparts; q += 8) {
+            int64_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * nb + t];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                part[(int64_t)(q + u) * nb + t] = run;
+                run += v[u];
+            }
+        }
+        for (; q < nparts; ++q) {
+            const int64_t v = part[(int64_t)q * nb + t];
+            part[(int64_t)q * nb + t] = run;
+            run += v;
+        }
+    }
+    int64_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t x = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += x;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int64_t excl = incl - run;
+    for (int u = 0; u < wave; ++u) excl += wsum[u];
+    if (t < nb) {
+        bstart[t] = excl;
+        for (int32_t q = 0; q < nparts; ++q) part[(int64_t)q * nb + t] += excl;
+    }
+    if (t == 0) bstart[nb] = nnz;
 }
 
 // Packed entries: when a slot's offset inside its bucket (rb bits) and a
@@ -573,8 +646,9 @@ __device__ __forceinline__ int32_t tp_col_of(int32_t word, int rb) {
 // threads per block; MB bounds the bucket count (the LDS tables are sized by
 // it, so the small form leaves room for more blocks per CU).
 template <bool POS, int NT, int MB, bool PACK>
-__global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
-                                                   const int64_t* __restrict__ off) {
+__global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t S,
+                                                   const int64_t* __restrict__ part,
+                                                   const int32_t* __restrict__ local) {
     constexpr int U = kTpTile / NT, NW = NT / 64;
     __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[MB], start[MB], base[MB];
@@ -587,9 +661,9 @@ __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_
     // and a running maximum along the tile (columns do not decrease along the
     // entries; an empty column starts where the next one does and loses).
     int32_t* mark = s_col;  // free until the placement below
-    for (int b = threadIdx.x; b < nb; b += NT) {
+    for (int b = threadIdx.x; b < nb; b += NT) {  // rows of the scanned tables: coalesced
         hist[b] = 0;
-        base[b] = (int32_t)off[(int64_t)b * nseg + seg];
+        base[b] = (int32_t)(part[(int64_t)(seg / S) * nb + b] + local[(int64_t)seg * nb + b]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) mark[threadIdx.x + NT * u] = -1;
@@ -681,15 +755,14 @@ __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_
 constexpr int kTpSub = 64;
 
 template <bool POS, bool PACK>
-__global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_t nb, int32_t nseg,
-                                                   const int64_t* __restrict__ off) {
+__global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_t nb,
+                                                   const int64_t* __restrict__ bstart) {
     __shared__ int32_t s_slot[kTpTile], s_col[PACK ? 1 : kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[kTpSub], start[kTpSub], cursor[kTpSub];
     const int32_t b = blockIdx.x;
     const int64_t r0 = (int64_t)b << rb;
     const int sb = rb - 6;
-    const int64_t e0 = off[(int64_t)b * nseg];
-    const int64_t e1 = (b + 1 < nb) ? off[(int64_t)(b + 1) * nseg] : A.nnz;
+    const int64_t e0 = bstart[b], e1 = bstart[b + 1];
     const int t = threadIdx.x;
     if (t < kTpSub) hist[t] = 0;
     __syncthreads();
@@ -900,38 +973,40 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     }
 }
 
-// Passes 1b-3 (scatter, split, place) in one of their forms.
+// Passes 1b-3 (scatter, split, place) in one of their forms; S tiles per
+// part of the column scan.
 template <bool POS, bool PACK>
-void launch_tp_sort(const Csc& A, const Work& W, const TpPlan& P, hipStream_t s) {
+void launch_tp_sort(const Csc& A, const Work& W, const TpPlan& P, int32_t S, hipStream_t s) {
     const int32_t nb = (int32_t)P.nb, nseg = (int32_t)P.nseg;
     constexpr int NT = kTpScatterThreads;
     if (nb <= 256)
-        hipLaunchKernelGGL((k_tp_scatter<POS, NT, 256, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+        hipLaunchKernelGGL((k_tp_scatter<POS, NT, 256, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, S, W.tp_off,
+                           W.tp_cnt);
     else
-        hipLaunchKernelGGL((k_tp_scatter<POS, NT, kTpMaxBuckets, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, nseg,
-                           W.tp_off);
-    hipLaunchKernelGGL((k_tp_split<POS, PACK>), dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, nseg, W.tp_off);
+        hipLaunchKernelGGL((k_tp_scatter<POS, NT, kTpMaxBuckets, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, S,
+                           W.tp_off, W.tp_cnt);
+    hipLaunchKernelGGL((k_tp_split<POS, PACK>), dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, W.tp_bstart);
     hipLaunchKernelGGL((k_tp_place<POS, PACK>), dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
 }
 
 hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions, hipStream_t s, int cus) {
     const TpPlan P = tp_plan(A.n, A.nnz);
     const int32_t nb = (int32_t)P.nb, nseg = (int32_t)P.nseg;
-    const int64_t m = P.nb * P.nseg;
     hipLaunchKernelGGL(k_tp_tile_cols, dim3(cus * 8), dim3(256), 0, s, A, W, nseg);
     hipLaunchKernelGGL(k_tp_hist, dim3(nseg), dim3(256), 0, s, A, W, P.rb, nb, nseg, W.tp_cnt);
-    const int64_t sb = (m + 2047) / 2048;
-    hipLaunchKernelGGL(k_scan_local, dim3((unsigned)sb), dim3(256), 0, s, W.tp_cnt, m, W.tp_off, W.tp_sums);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, W.tp_sums, sb, W.tp_off + m);
-    hipLaunchKernelGGL(k_scan_add, dim3(cus * 8), dim3(256), 0, s, W.tp_off, m, W.tp_sums);
+    // column scan in parts of S tiles (about 128 parts)
+    const int32_t S = nseg / 128 + 1 > 32 ? nseg / 128 + 1 : 32;
+    const int32_t nparts = (nseg + S - 1) / S;
+    hipLaunchKernelGGL(k_tp_colsum, dim3(nparts), dim3(256), 0, s, W.tp_cnt, nb, nseg, S, W.tp_off);
+    hipLaunchKernelGGL(k_tp_colscan, dim3(1), dim3(1024), 0, s, W.tp_off, nb, nparts, W.tp_bstart, A.nnz);
     // a slot's offset in its bucket and a column share one word when they fit
     const bool pack = (int64_t)A.n <= ((int64_t)1 << (32 - P.rb));
     if (positions) {
-        if (pack) launch_tp_sort<true, true>(A, W, P, s);
-        else launch_tp_sort<true, false>(A, W, P, s);
+        if (pack) launch_tp_sort<true, true>(A, W, P, S, s);
+        else launch_tp_sort<true, false>(A, W, P, S, s);
     } else {
-        if (pack) launch_tp_sort<false, true>(A, W, P, s);
-        else launch_tp_sort<false, false>(A, W, P, s);
+        if (pack) launch_tp_sort<false, true>(A, W, P, S, s);
+        else launch_tp_sort<false, false>(A, W, P, S, s);
     }
     return hipGetLastError();
 }
@@ -1205,6 +1280,7 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.tp_pos = (int32_t*)take(tpz * 4);
     W.tp_cnt = (int32_t*)take(tpm * 4);
     W.tp_off = (int64_t*)take((tpm + 1) * 8);
+    W.tp_bstart = (int64_t*)take((kTpMaxBuckets + 1) * 8);
     W.tp_sums = (int64_t*)take((tpm / 2048 + 2) * 8);
     W.tp_row2 = (int32_t*)take(tpz * 4);
     W.tp_col2 = (int32_t*)take(tpz * 4);

@@ -201,13 +201,19 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     if (h->host[kErrMatch]) return HWPM_EBADMATCH;
     if (BP) HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_init, s, h->cus));
     const int32_t n_long = h->host[kNumLong];
+    // hash tables of the long row lists only for matrices with long columns
+    // (where long row lists occur on real patterns); elsewhere the rounds see
+    // no tables and the pass that fills them is not launched
+    if (n_long == 0) Wr.rtab = nullptr;
     if (n_long > 0) HIP_TRY(launch_long_chunks(W, A, s));
     S.long_columns = n_long;
     memcpy(&S.init_weight, h->host + kHostScalar, sizeof(double));
     if (transposed) {
         if (timing) HIP_TRY(hipEventRecord(ev[2], s));
         if (incremental) HIP_TRY(hipMemsetAsync(W.dirty, 0, (size_t)n * sizeof(int32_t), s));
-        HIP_TRY(launch_transpose(A, W, kLongThreshold, n_long > 0, !light, s, h->cus));
+        Work Wt = W;
+        Wt.rtab = Wr.rtab;
+        HIP_TRY(launch_transpose(A, Wt, kLongThreshold, n_long > 0, !light, s, h->cus));
         if (timing) HIP_TRY(hipEventRecord(ev[3], s));  // read at the end
     }
 
@@ -273,7 +279,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
             HIP_TRY(launch_collect(A, W, slot, st, h->cus));
             HIP_TRY(launch_resolve(W, slot, st, h->cus));
             if (timing) HIP_TRY(hipEventRecord(e[2], st));
-            HIP_TRY(launch_apply(A, W, slot, transposed, st, h->cus));
+            HIP_TRY(launch_apply(A, Wr, slot, transposed, st, h->cus));
             if (transposed) HIP_TRY(launch_mrk_update(A, Wr, slot, incremental, st, h->cus));
             if (BP) HIP_TRY(launch_item_rounds(*BP, W.counters + kDone, st));
             if (timing) HIP_TRY(hipEventRecord(e[3], st));

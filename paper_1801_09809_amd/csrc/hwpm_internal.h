@@ -23,6 +23,8 @@ enum CounterWord : int {
     kRoundsRun = 5,    // search passes run so far
     kCycles = 6,       // u64 in words 6-7: cycles flipped in all rounds
     kRoundBase = 8,    // per-round words, kSlotWords per slot of the ring
+    kTabUsed = 72,     // u64 in words 72-73: pool words taken by the row-list hash tables
+    kTabRows = 74,     // row lists that got a hash table
     kSpreadBase = 128, // sub-list counters of the wave-per-root hand-off (below)
 };
 
@@ -43,6 +45,10 @@ __host__ __device__ inline int slot_word(int slot, int w) { return kRoundBase + 
 // counter address.  Sub-list s of a round holds at most `cap` roots, at
 // medium[s * cap ...).
 constexpr int kSpread = 64;
+
+// Row lists longer than this get a hash table in global memory (column ->
+// place in the list; built once per call, after the transpose).
+constexpr int kRowSetMin = 2048;
 constexpr int kSpreadStride = 32;  // words between two sub-list counters
 constexpr int kCounterWords = kSpreadBase + kSlots * kSpread * kSpreadStride;
 __host__ __device__ inline int spread_word(int slot, int s) {
@@ -112,6 +118,9 @@ struct Work {
     int32_t* cscpos;    // nnz: CSC position of each row-list entry (transposed probes need nnz < 2^31);
                         // null when the lists are built without positions (probe 5)
     int32_t* mrk;       // nnz: m_i of the row of CSC entry k
+    int32_t* rtab;      // n: offset in tabs of the hash table of the row list at slot j (-1: none);
+                        // moves with rsl; null when the solve keeps no tables
+    int32_t* tabs;      // nnz + 64: pool of the hash tables of the long row lists (keys, then values)
     int32_t* rowcnt;    // n: row counts, then fill cursors
     int64_t* scan_sums; // block sums of the row-count scan
     int32_t* flips;     // 4 per flipped cycle: (i, new mate j), (l, new mate c)

@@ -287,6 +287,11 @@ __global__ void k_apply(Csc A, Work W, int slot, int transposed) {
             const int2 sj = W.rsl[j], sc = W.rsl[c];
             W.rsl[j] = sc;
             W.rsl[c] = sj;
+            if (W.rtab) {
+                const int32_t tj = W.rtab[j], tc = W.rtab[c];
+                W.rtab[j] = tc;
+                W.rtab[c] = tj;
+            }
             W.pm[j] = (int32_t)W.best_k[j];
             W.pm[c] = (int32_t)W.best_p[j];
         }
@@ -422,10 +427,31 @@ __global__ __launch_bounds__(256) void k_row_fill_long(Csc A, Work W) {
 
 // Slot pointers of the row lists: rsl[j] = (start, length) of the list of
 // the row matched to j.
+// Hash tables of the long row lists (filled by k_rowset_fill, see there):
+// the table words a list of len entries takes from the pool of nnz + 64
+// words, or -1 (short list, or no room left).
+__device__ __forceinline__ int32_t rowset_take(const Work& W, int32_t len, int64_t nnz) {
+    if (len <= kRowSetMin) return -1;
+    unsigned long long size = 64;
+    while (size < 2ull * (unsigned long long)len) size <<= 1;
+    const unsigned long long at = atomicAdd(reinterpret_cast<unsigned long long*>(W.counters + kTabUsed), 2 * size);
+    return at + 2 * size <= (unsigned long long)nnz + 64 ? (int32_t)at : -1;
+}
+
+// Record slot j's table (or none) and list it for filling.  All active lanes
+// of the wave call it together.
+__device__ __forceinline__ void rowset_note(const Work& W, int32_t j, int32_t off, bool valid) {
+    if (valid) W.rtab[j] = off;
+    const int32_t q = wave_append(&W.counters[kTabRows], valid && off >= 0);
+    if (valid && off >= 0) W.medium[q] = j;  // the buffer is free until the rounds
+}
+
 __global__ void k_slot_ptrs(Csc A, Work W) {
     for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < A.n;
          j += (int64_t)gridDim.x * blockDim.x) {
-        W.rsl[j] = make_int2((int32_t)W.rowptr[j], (int32_t)(W.rowptr[j + 1] - W.rowptr[j]));
+        const int32_t len = (int32_t)(W.rowptr[j + 1] - W.rowptr[j]);
+        W.rsl[j] = make_int2((int32_t)W.rowptr[j], len);
+        if (W.rtab) rowset_note(W, (int32_t)j, rowset_take(W, len, A.nnz), true);  // grid-uniform
     }
 }
 
@@ -912,6 +938,11 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
             W.rowptr[s0 + 2 * t + 1] = e0 + ex + a0;
             W.rsl[s0 + 2 * t + 1] = make_int2((int32_t)(e0 + ex + a0), a1);
         }
+        if (W.rtab) {  // the whole first wave: the long lists' hash tables
+            rowset_note(W, (int32_t)(s0 + 2 * t), 2 * t < nr ? rowset_take(W, a0, A.nnz) : -1, 2 * t < nr);
+            rowset_note(W, (int32_t)(s0 + 2 * t + 1), 2 * t + 1 < nr ? rowset_take(W, a1, A.nnz) : -1,
+                        2 * t + 1 < nr);
+        }
     }
     if (g == nb * kTpSub - 1 && t == 0) W.rowptr[A.n] = A.nnz;
     __syncthreads();
@@ -1011,6 +1042,45 @@ hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions,
     return hipGetLastError();
 }
 
+// Hash tables of the long row lists.  A row list never changes during a call
+// (a flip moves it from one slot to another), so every list longer than
+// kRowSetMin entries gets, once, a table in global memory mapping each of its
+// columns to its place in the list (size pow2 >= 2 x length, load <= 1/2:
+// the keys, then the values), and the probes of its roots find the closing
+// edge with a load or two (and its CSC position through the list's stored
+// positions) instead of a binary search of column m_i.  rtab[j] locates the
+// table of the list at slot j and moves with rsl.  The tables take their
+// words from a pool of nnz + 64 words, first come first served; a list that
+// finds no room keeps rtab = -1 and the binary search.
+struct GlobalCas32 {
+    __device__ int32_t operator()(int32_t* p, int32_t e, int32_t d) const { return atomicCAS(p, e, d); }
+};
+
+__global__ __launch_bounds__(256) void k_rowset_fill(Work W) {
+    const int32_t nr = W.counters[kTabRows];
+    for (int32_t q = blockIdx.x; q < nr; q += gridDim.x) {  // block-uniform
+        const int32_t j = W.medium[q];
+        const int2 rl = W.rsl[j];
+        int32_t* tab = W.tabs + W.rtab[j];
+        uint32_t size = 64;
+        while ((int32_t)size < 2 * rl.y) size <<= 1;
+        for (uint32_t x = threadIdx.x; x < size; x += blockDim.x) tab[x] = -1;
+        __threadfence();
+        __syncthreads();
+        bool ok = true;
+        for (int32_t x = threadIdx.x; x < rl.y; x += blockDim.x)
+            ok &= hash_insert(tab, tab + size, W.colidx[rl.x + x], x, size - 1, GlobalCas32{});
+        // a list the table cannot take (impossible with a well-formed CSC)
+        // keeps the binary search
+        if (__syncthreads_or(!ok) && threadIdx.x == 0) W.rtab[j] = -1;
+    }
+}
+
+hipError_t launch_rowsets(const Csc& A, const Work& W, hipStream_t s, int cus) {
+    if (W.rtab) hipLaunchKernelGGL(k_rowset_fill, dim3(cus), dim3(256), 0, s, W);
+    return hipGetLastError();
+}
+
 bool transpose_without_positions(int64_t n, int64_t nnz) { return tp_plan(n, nnz).ok; }
 
 hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
@@ -1019,7 +1089,8 @@ hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold,
     hipError_t e;
     if (tp_plan(A.n, A.nnz).ok) {
         // also fills mrk
-        return launch_transpose_buckets(A, W, positions, s, cus);
+        if ((e = launch_transpose_buckets(A, W, positions, s, cus)) != hipSuccess) return e;
+        return launch_rowsets(A, W, s, cus);
     } else {
         // very large matrices: counting sort with global atomics
         if ((e = hipMemsetAsync(W.rowcnt, 0, (size_t)n * sizeof(int32_t), s)) != hipSuccess) return e;
@@ -1037,7 +1108,8 @@ hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold,
         hipLaunchKernelGGL(k_slot_ptrs, dim3(cus * 8), dim3(256), 0, s, A, W);
     }
     if (A.nnz > 0) hipLaunchKernelGGL(k_mrk_fill, dim3(cus * 8), dim3(256), 0, s, A, W);
-    return hipGetLastError();
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_rowsets(A, W, s, cus);
 }
 
 // After the flips of a round: the entries of every row whose mate changed get
@@ -1263,6 +1335,8 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.colidx = (int32_t*)take(Z * 4 + 128);
     W.cscpos = (int32_t*)take(Z * 4);
     W.mrk = (int32_t*)take(Z * 4 + 128);
+    W.rtab = (int32_t*)take(N * 4);
+    W.tabs = (int32_t*)take((Z + 64) * 4);
     W.rowcnt = (int32_t*)take(N * 4);
     W.scan_sums = (int64_t*)take((N / 2048 + 2) * 8);
     W.flips = (int32_t*)take(N * 4 * 4 / 2 + 16);

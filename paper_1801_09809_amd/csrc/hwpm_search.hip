@@ -107,7 +107,30 @@ __global__ __launch_bounds__(256) void k_search_long(Csc A, Work W, int only_dir
             }
             __syncthreads();  // the set is rebuilt for the next chunk
         }
-        if (!hashed && start < hi) {
+        const int32_t tb = transposed && !hashed && W.rtab ? W.rtab[j] : -1;  // block-uniform
+        if (!hashed && start < hi && tb >= 0) {
+            // the list's hash table: a probe that hits reads its position
+            // (or, without stored positions, searches for it)
+            uint32_t size = 64;
+            while ((int32_t)size < 2 * rl.y) size <<= 1;
+            const int32_t* tab = W.tabs + tb;
+            for (int64_t k0 = start + threadIdx.x; k0 < hi; k0 += 4 * (int64_t)blockDim.x) {
+                int32_t cq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t k = k0 + (int64_t)q * blockDim.x;
+                    cq[q] = (k < hi) ? W.mrk[k] : -1;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t qx = cq[q] < 0 ? -1 : hash_find(tab, tab + size, cq[q], size - 1);
+                    if (qx < 0) continue;
+                    const int64_t k = k0 + (int64_t)q * blockDim.x;
+                    const int64_t p = W.cscpos ? (int64_t)W.cscpos[rl.x + qx] : find_row(A.col_ptr, A.row_idx, cq[q], mj);
+                    if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[cq[q]] + W.wm[j]), k, cq[q], p);
+                }
+            }
+        } else if (!hashed && start < hi) {
             // four entries per thread, their binary searches in lockstep
             const int32_t step = blockDim.x;
             for (int64_t k0 = start + threadIdx.x; k0 < hi; k0 += 4 * (int64_t)step) {
@@ -584,7 +607,31 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot, 
                 for (int32_t k = s0 + 64 * kHashPre + lane; k < hi; k += 64) probe(k, W.mrk[k]);
             }
         }
-        if (!hashed) {
+        const int32_t tb = hashed || !W.rtab ? -1 : W.rtab[j];  // wave-uniform
+        if (!hashed && tb >= 0) {
+            // the list's hash table: a probe that hits reads its position
+            // (or, without stored positions, searches for it)
+            const int32_t mj = W.mc[j];
+            uint32_t size = 64;
+            while ((int32_t)size < 2 * rl.y) size <<= 1;
+            const int32_t* tab = W.tabs + tb;
+            for (int32_t k0 = s0 + lane; k0 < hi; k0 += 4 * 64) {
+                int32_t cq[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t k = k0 + 64 * q;
+                    cq[q] = (k < hi) ? W.mrk[k] : -1;
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t qx = cq[q] < 0 ? -1 : hash_find(tab, tab + size, cq[q], size - 1);
+                    if (qx < 0) continue;
+                    const int32_t k = k0 + 64 * q;
+                    const int64_t p = W.cscpos ? (int64_t)W.cscpos[rl.x + qx] : find_row(A.col_ptr, A.row_idx, cq[q], mj);
+                    if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[cq[q]] + W.wm[j]), k, cq[q], p);
+                }
+            }
+        } else if (!hashed) {
             // four entries per lane, their binary searches in lockstep
             const int32_t mj = W.mc[j];
             for (int32_t k0 = s0 + lane; k0 < hi; k0 += 4 * 64) {

@@ -25,6 +25,7 @@ enum CounterWord : int {
     kRoundBase = 8,    // per-round words, kSlotWords per slot of the ring
     kTabUsed = 72,     // u64 in words 72-73: pool words taken by the row-list hash tables
     kTabRows = 74,     // row lists that got a hash table
+    kColDone = 75,     // buckets whose column scan has finished (the transpose's part 2)
     kSpreadBase = 128, // sub-list counters of the wave-per-root hand-off (below)
 };
 
@@ -135,8 +136,10 @@ struct Work {
     int32_t* tp_col;
     int32_t* tp_pos;
     int32_t* tp_cnt;    // tile-major (tile, bucket) counts, then their scan inside each part of tiles
-    int64_t* tp_off;    // per (part of tiles, bucket): where its entries of that bucket begin
+    int64_t* tp_off;    // per (part of tiles, bucket): where its entries of that bucket begin,
+                        // counted from the bucket's start
     int64_t* tp_bstart; // bucket starts (+ nnz)
+    int64_t* tp_btot;   // bucket totals
     int64_t* tp_sums;
     int32_t* tp_row2;   // pass-2 output, grouped by sub-bucket
     int32_t* tp_col2;

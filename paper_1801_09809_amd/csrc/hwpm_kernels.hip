@@ -613,48 +613,53 @@ __global__ __launch_bounds__(256) void k_tp_colsum(int32_t* __restrict__ cnt, in
     }
 }
 
-// Part 2, one block, one bucket per thread (nb <= 1024): the parts' sums of
-// each bucket scanned down the parts, the bucket totals scanned across the
-// buckets (bstart, with bstart[nb] = nnz), and each part's value turned into
-// the global position where its entries of that bucket begin.
-__global__ __launch_bounds__(1024) void k_tp_colscan(int64_t* __restrict__ part, int32_t nb, int32_t nparts,
-                                                     int64_t* __restrict__ bstart, int64_t nnz) {
-    __shared__ int64_t wsum[16];
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+// Part 2: a wave per bucket scans the parts' sums down the parts (each
+// part's value becomes where its entries of that bucket begin, counted from
+// the bucket's start), and the last wave to finish scans the bucket totals
+// across the buckets (bstart, with bstart[nb] = nnz).  Spread over the grid,
+// the table's reads and writes are not bound by one CU's bandwidth.
+__global__ __launch_bounds__(64) void k_tp_colscan(int64_t* __restrict__ part, int32_t nb, int32_t nparts,
+                                                   int64_t* __restrict__ btot, int64_t* __restrict__ bstart,
+                                                   int64_t nnz, int32_t* __restrict__ done) {
+    const int32_t b = blockIdx.x;
+    const int lane = threadIdx.x;
+    int64_t carry = 0;
+    for (int32_t q0 = 0; q0 < nparts; q0 += 64) {
+        const int32_t q = q0 + lane;
+        const int64_t v = q < nparts ? part[(int64_t)q * nb + b] : 0;
+        int64_t incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t x = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += x;
+        }
+        if (q < nparts) part[(int64_t)q * nb + b] = carry + incl - v;
+        carry += __shfl(incl, 63, 64);
+    }
+    int32_t ticket = 0;
+    if (lane == 0) {
+        __hip_atomic_store(&btot[b], carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ticket = __hip_atomic_fetch_add(done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    ticket = __shfl(ticket, 0, 64);
+    if (ticket != nb - 1) return;  // wave-uniform: not the last bucket's wave
     int64_t run = 0;
-    if (t < nb) {
-        int32_t q = 0;
-        for (; q + 8 <= nparts; q += 8) {
-            int64_t v[8];
+    for (int32_t b0 = 0; b0 < nb; b0 += 64) {
+        const int32_t bb = b0 + lane;
+        const int64_t v = bb < nb ? __hip_atomic_load(&btot[bb], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+        int64_t incl = v;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * nb + t];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                part[(int64_t)(q + u) * nb + t] = run;
-                run += v[u];
-            }
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t x = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += x;
         }
-        for (; q < nparts; ++q) {
-            const int64_t v = part[(int64_t)q * nb + t];
-            part[(int64_t)q * nb + t] = run;
-            run += v;
-        }
+        if (bb < nb) bstart[bb] = run + incl - v;
+        run += __shfl(incl, 63, 64);
     }
-    int64_t incl = run;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int64_t x = __shfl_up(incl, o, 64);
-        if (lane >= o) incl += x;
+    if (lane == 0) {
+        bstart[nb] = nnz;
+        *done = 0;
     }
-    if (lane == 63) wsum[wave] = incl;
-    __syncthreads();
-    int64_t excl = incl - run;
-    for (int u = 0; u < wave; ++u) excl += wsum[u];
-    if (t < nb) {
-        bstart[t] = excl;
-        for (int32_t q = 0; q < nparts; ++q) part[(int64_t)q * nb + t] += excl;
-    }
-    if (t == 0) bstart[nb] = nnz;
 }
 
 // Packed entries: when a slot's offset inside its bucket (rb bits) and a
@@ -674,7 +679,8 @@ __device__ __forceinline__ int32_t tp_col_of(int32_t word, int rb) {
 template <bool POS, int NT, int MB, bool PACK>
 __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_t nb, int32_t S,
                                                    const int64_t* __restrict__ part,
-                                                   const int32_t* __restrict__ local) {
+                                                   const int32_t* __restrict__ local,
+                                                   const int64_t* __restrict__ bstart) {
     constexpr int U = kTpTile / NT, NW = NT / 64;
     __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[MB], start[MB], base[MB];
@@ -689,7 +695,7 @@ __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_
     int32_t* mark = s_col;  // free until the placement below
     for (int b = threadIdx.x; b < nb; b += NT) {  // rows of the scanned tables: coalesced
         hist[b] = 0;
-        base[b] = (int32_t)(part[(int64_t)(seg / S) * nb + b] + local[(int64_t)seg * nb + b]);
+        base[b] = (int32_t)(bstart[b] + part[(int64_t)(seg / S) * nb + b] + local[(int64_t)seg * nb + b]);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) mark[threadIdx.x + NT * u] = -1;
@@ -1012,10 +1018,10 @@ void launch_tp_sort(const Csc& A, const Work& W, const TpPlan& P, int32_t S, hip
     constexpr int NT = kTpScatterThreads;
     if (nb <= 256)
         hipLaunchKernelGGL((k_tp_scatter<POS, NT, 256, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, S, W.tp_off,
-                           W.tp_cnt);
+                           W.tp_cnt, W.tp_bstart);
     else
         hipLaunchKernelGGL((k_tp_scatter<POS, NT, kTpMaxBuckets, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, S,
-                           W.tp_off, W.tp_cnt);
+                           W.tp_off, W.tp_cnt, W.tp_bstart);
     hipLaunchKernelGGL((k_tp_split<POS, PACK>), dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, W.tp_bstart);
     hipLaunchKernelGGL((k_tp_place<POS, PACK>), dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
 }
@@ -1029,7 +1035,8 @@ hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions,
     const int32_t S = nseg / 128 + 1 > 32 ? nseg / 128 + 1 : 32;
     const int32_t nparts = (nseg + S - 1) / S;
     hipLaunchKernelGGL(k_tp_colsum, dim3(nparts), dim3(256), 0, s, W.tp_cnt, nb, nseg, S, W.tp_off);
-    hipLaunchKernelGGL(k_tp_colscan, dim3(1), dim3(1024), 0, s, W.tp_off, nb, nparts, W.tp_bstart, A.nnz);
+    hipLaunchKernelGGL(k_tp_colscan, dim3(nb), dim3(64), 0, s, W.tp_off, nb, nparts, W.tp_btot, W.tp_bstart, A.nnz,
+                       W.counters + kColDone);
     // a slot's offset in its bucket and a column share one word when they fit
     const bool pack = (int64_t)A.n <= ((int64_t)1 << (32 - P.rb));
     if (positions) {
@@ -1355,6 +1362,7 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.tp_cnt = (int32_t*)take(tpm * 4);
     W.tp_off = (int64_t*)take((tpm + 1) * 8);
     W.tp_bstart = (int64_t*)take((kTpMaxBuckets + 1) * 8);
+    W.tp_btot = (int64_t*)take(kTpMaxBuckets * 8);
     W.tp_sums = (int64_t*)take((tpm / 2048 + 2) * 8);
     W.tp_row2 = (int32_t*)take(tpz * 4);
     W.tp_col2 = (int32_t*)take(tpz * 4);

@@ -4,9 +4,9 @@ folder, and derive the HBM traffic of a kernel from two counter passes.
     python -m paper_1801_09809_amd.profsummary trace RESULTS.db --command "..."
     python -m paper_1801_09809_amd.profsummary pmc --fetch FETCH.db --write WRITE.db --copy-bytes N
     python -m paper_1801_09809_amd.profsummary traffic --fetch FETCH.db --write WRITE.db \
-        --kernel k_search_chunk,k_search_medium --name search_stage --copy-bytes N \
-        --source csrc/hwpm_search.hip,csrc/hwpm_device.h,csrc/hwpm_internal.h \
-        --workload random_n1048576_d16 --probe 3 --out profiles/traffic.json
+        --kernel k_search_filter,k_search_medium --name search_stage --copy-bytes N \
+        --source csrc/hwpm_search.hip,csrc/hwpm_device.h,csrc/hwpm_hash.h,csrc/hwpm_internal.h \
+        --workload random_n1048576_d16 --probe 5 --out profiles/traffic.json
 
 Reads only the SQLite files rocprofv3 writes (views `kernels` and
 `counters_collection`).  Counter values are summed over the rows of one

@@ -303,6 +303,26 @@ __device__ __forceinline__ int32_t wave_max(int32_t v) {
     return __builtin_amdgcn_readlane(v, 63);
 }
 
+// Element idx of an array of at most 2^32 bytes.  With O32 the byte offset
+// is a 32-bit value added to the array's base, so the load takes the base
+// from scalar registers and a 32-bit offset per lane, with no 64-bit address
+// arithmetic in the vector unit (the tile kernels are bound by vector
+// instruction issue).
+template <bool O32, typename V>
+__device__ __forceinline__ V ld_at(const V* base, int32_t idx) {
+    if constexpr (O32)
+        return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) +
+                                           (uint32_t)idx * (uint32_t)sizeof(V));
+    else
+        return base[idx];
+}
+
+// The element at byte offset off of an array of at most 2^32 bytes.
+template <typename V>
+__device__ __forceinline__ V ld_byte(const V* base, uint32_t off) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + off);
+}
+
 // The per-root values of a tile kernel, read together (one memory round trip).
 struct RootView {
     int32_t j, s0, slen;  // root, first position after the matched entry, suffix length
@@ -310,13 +330,14 @@ struct RootView {
     bool own;             // a short root of this kernel (long columns: the split kernel)
 };
 
+template <bool O32 = false>
 __device__ __forceinline__ RootView load_root(const Work& W, int64_t t, int64_t ntiles, const int32_t* roots,
                                               int32_t long_threshold) {
     RootView r;
     const bool in = t < ntiles;
-    r.j = in ? (roots ? roots[t] : (int32_t)t) : 0;
-    const int32_t lo = W.cp32[r.j], hi = W.cp32[r.j + 1], pmj = W.pm[r.j];
-    r.rl = W.rsl[r.j];
+    r.j = in ? (roots ? ld_at<O32>(roots, (int32_t)t) : (int32_t)t) : 0;
+    const int32_t lo = ld_at<O32>(W.cp32, r.j), hi = ld_at<O32>(W.cp32, r.j + 1), pmj = ld_at<O32>(W.pm, r.j);
+    r.rl = ld_at<O32>(W.rsl, r.j);
     r.own = in && hi - lo <= long_threshold;
     r.s0 = pmj + 1;  // rows i > m_j: the positions after the matched entry
     r.slen = r.own ? hi - r.s0 : 0;
@@ -387,16 +408,19 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
 // Probes 3 and 5: transposed lists, filter form (the default).  A tile of T
 // lanes per root loads the pruned suffix of column j (E mate columns per
 // lane) and the row list of m_j (E columns per lane), all loads independent.
-// The tile ORs its row list into a two-word filter (one bit per word, from
-// two multiplicative hashes of the column), and each probe m_i whose two bits
+// The tile ORs its row list into a two-word filter (one bit per 64-bit word,
+// from two fields of one hash of the column), and each probe m_i whose two bits
 // are both set is compared exactly with the whole row list, gathered once
 // into every lane of the tile; the others are certain misses.  With about 17
 // columns in a row list a miss passes the filter about 5 % of the time, so
 // on matrices whose probes mostly miss the exact comparisons shrink from
 // every pair to a few probes per wave.  Roots whose suffix or row list
 // exceeds T * E entries are handed off.
-__device__ __forceinline__ uint32_t filter_bit1(int32_t c) { return ((uint32_t)c * 0x9E3779B1u) >> 26; }
-__device__ __forceinline__ uint32_t filter_bit2(int32_t c) { return ((uint32_t)c * 0x85EBCA6Bu) >> 26; }
+// One multiplicative hash of the column's low 24 bits (a full-rate 24-bit
+// multiply); its bits 26-31 and 20-25 pick the bits of the two filter words.
+// Columns that agree in their low 24 bits share their bits, which can only
+// let more probes through to the exact comparison.
+__device__ __forceinline__ uint32_t filter_hash(int32_t c) { return __umul24((uint32_t)c, 0x9E3779u); }
 
 // A root whose suffix and row list exceed the tile but fit the wave's 64
 // lanes: the whole wave searches it, one suffix entry and one list entry per
@@ -429,7 +453,7 @@ template <int T>
 constexpr int kWideMax = T == 4 ? 2 : 0;
 
 // Steps A-C of one group of 64 / T roots (a tile per root); see below.
-template <int T, int E>
+template <int T, int E, bool O32>
 __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const RootView& r, int slot, int sub,
                                              int32_t cap, bool listed) {
     const int l64 = threadIdx.x & 63;
@@ -444,30 +468,39 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
     const bool wide = (wm >> l64) & 1u;
     hand_off(W, slot, sub, cap, r.j, big && !wide && lane == 0);
     const bool search = r.slen > 0 && !big;
-    // loads, only as far as the wave's longest suffix and row list go:
-    // indices clamped into the segment (the matched entry and the list's
-    // first entry always exist), values past it masked
+    // loads, only as far as the wave's longest suffix and row list go,
+    // indices clamped to the last entry of the segment: a lane's entries past
+    // the end repeat that entry (an empty suffix reads the matched entry; a
+    // row list always holds the matched entry of its row)
     const int32_t e_lim = (wave_max(search ? r.slen : 0) + T - 1) / T;
     const int32_t f_lim = (wave_max(search ? r.rl.y : 0) + T - 1) / T;
     int32_t mv[E], rv[E];
+    if constexpr (O32) {  // byte offsets
+        const uint32_t m0 = (uint32_t)(r.s0 + lane) * 4u, m1 = (uint32_t)(r.s0 + r.slen - 1) * 4u;
+        const uint32_t c0 = (uint32_t)(r.rl.x + lane) * 4u, c1 = (uint32_t)(r.rl.x + r.rl.y - 1) * 4u;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int32_t x = lane + T * e;
-        mv[e] = e < e_lim ? W.mrk[x < r.slen ? r.s0 + x : r.s0 - 1] : -1;
-        rv[e] = e < f_lim ? W.colidx[x < r.rl.y ? r.rl.x + x : r.rl.x] : -2;
-    }
-    uint32_t f1lo = 0, f1hi = 0, f2lo = 0, f2hi = 0;
+        for (int e = 0; e < E; ++e) {
+            mv[e] = e < e_lim ? ld_byte(W.mrk, min(m0 + 4u * T * e, m1)) : -1;
+            rv[e] = e < f_lim ? ld_byte(W.colidx, min(c0 + 4u * T * e, c1)) : -2;
+        }
+    } else {
+        const int64_t m1 = (int64_t)r.s0 + r.slen - 1, c1 = (int64_t)r.rl.x + r.rl.y - 1;
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int32_t x = lane + T * e;
-        if (!(search && x < r.slen)) mv[e] = -1;
-        if (!(search && x < r.rl.y)) rv[e] = -2;
-        if (rv[e] >= 0) {
-            const uint32_t b1 = filter_bit1(rv[e]), b2 = filter_bit2(rv[e]);
-            if (b1 < 32) f1lo |= 1u << b1; else f1hi |= 1u << (b1 - 32);
-            if (b2 < 32) f2lo |= 1u << b2; else f2hi |= 1u << (b2 - 32);
+        for (int e = 0; e < E; ++e) {
+            mv[e] = e < e_lim ? W.mrk[min((int64_t)r.s0 + lane + T * e, m1)] : -1;
+            rv[e] = e < f_lim ? W.colidx[min((int64_t)r.rl.x + lane + T * e, c1)] : -2;
         }
     }
+    // the filter of the row list (the repeated last entry adds no bits)
+    uint64_t f1 = 0, f2 = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (e >= f_lim) break;  // wave-uniform
+        const uint32_t h = filter_hash(rv[e]);
+        f1 |= 1ull << (h >> 26);
+        f2 |= 1ull << ((h >> 20) & 63);
+    }
+    uint32_t f1lo = (uint32_t)f1, f1hi = (uint32_t)(f1 >> 32), f2lo = (uint32_t)f2, f2hi = (uint32_t)(f2 >> 32);
 #pragma unroll
     for (int sft = 1; sft < T; sft <<= 1) {
         f1lo |= (uint32_t)tile_xor<T>((int32_t)f1lo, sft);
@@ -475,14 +508,18 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
         f2lo |= (uint32_t)tile_xor<T>((int32_t)f2lo, sft);
         f2hi |= (uint32_t)tile_xor<T>((int32_t)f2hi, sft);
     }
+    f1 = ((uint64_t)f1hi << 32) | f1lo;
+    f2 = ((uint64_t)f2hi << 32) | f2lo;
+    // the probes against it; a lane's own probes are its first nm entries
+    const int32_t nm = search && r.slen > lane ? (r.slen - lane + T - 1) / T : 0;
     uint32_t pending = 0;  // bit e: probe e passed the filter
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        if (mv[e] < 0) continue;
-        const uint32_t b1 = filter_bit1(mv[e]), b2 = filter_bit2(mv[e]);
-        const uint32_t w1 = b1 < 32 ? f1lo : f1hi, w2 = b2 < 32 ? f2lo : f2hi;
-        if ((w1 >> (b1 & 31)) & (w2 >> (b2 & 31)) & 1u) pending |= 1u << e;
+        if (e >= e_lim) break;  // wave-uniform
+        const uint32_t h = filter_hash(mv[e]);
+        pending |= (uint32_t)((f1 >> (h >> 26)) & (f2 >> ((h >> 20) & 63)) & 1u) << e;
     }
+    pending &= (1u << nm) - 1u;
     Cand b{0.0, kNoPos, -1, -1};
     while (__ballot(pending != 0)) {  // wave-uniform: one passed probe per lane at a time
         const int e = pending ? __builtin_ctz(pending) : -1;
@@ -493,6 +530,8 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
             if (u == e) mi = mv[u];
         // the tile's probes, each compared by every lane with its own part
         // of the row list; the matching place comes back to the probe's lane
+        // (a match with a repeat of the list's last entry lies past the
+        // list's end and stands for that last entry)
         int32_t q = -1;
 #pragma unroll
         for (int src = 0; src < T; ++src) {
@@ -505,6 +544,7 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
             if (lane == src) q = xs;
         }
         if (q >= 0) {
+            q = min(q, r.rl.y - 1);
             const int32_t k = r.s0 + lane + T * e;
             const int64_t p = W.cscpos ? (int64_t)W.cscpos[r.rl.x + q] : find_row(A.col_ptr, A.row_idx, mi, W.mc[r.j]);
             if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[r.j]), k, mi, p);
@@ -517,8 +557,9 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
         search_wide(A, W, __builtin_amdgcn_readlane(r.j, __builtin_ctzll(wm)), l64);
 }
 
-// One group of 64 / T roots per wave.
-template <int T, int E>
+// One group of 64 / T roots per wave.  O32: every array the tiles index holds
+// at most 2^32 bytes (nnz < 2^30, n < 2^28).
+template <int T, int E, bool O32>
 __global__ __launch_bounds__(256, 8) void k_search_filter(Csc A, Work W, int32_t long_threshold, int slot,
                                                           const int32_t* __restrict__ roots, int32_t cap) {
     constexpr int kTiles = 64 / T;
@@ -526,8 +567,8 @@ __global__ __launch_bounds__(256, 8) void k_search_filter(Csc A, Work W, int32_t
     const int64_t ntiles = roots ? W.counters[slot_word(slot, kRoots)] : A.n;
     const int64_t grp = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     if (grp * kTiles >= ntiles) return;  // wave-uniform
-    const RootView r = load_root(W, grp * kTiles + (threadIdx.x & 63) / T, ntiles, roots, long_threshold);
-    search_group<T, E>(A, W, r, slot, (int)(blockIdx.x & (kSpread - 1)), cap, roots != nullptr);
+    const RootView r = load_root<O32>(W, grp * kTiles + (threadIdx.x & 63) / T, ntiles, roots, long_threshold);
+    search_group<T, E, O32>(A, W, r, slot, (int)(blockIdx.x & (kSpread - 1)), cap, roots != nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -657,6 +698,19 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot, 
     }
 }
 
+template <bool O32>
+static hipError_t launch_filter(const Csc& A, const Work& W, int tile_width, unsigned blocks, int32_t long_threshold,
+                                int slot, const int32_t* roots, int32_t cap, hipStream_t s) {
+    switch (tile_width) {
+        case 4: hipLaunchKernelGGL((k_search_filter<4, 8, O32>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+        case 8: hipLaunchKernelGGL((k_search_filter<8, 4, O32>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+        case 16: hipLaunchKernelGGL((k_search_filter<16, 2, O32>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+        case 32: hipLaunchKernelGGL((k_search_filter<32, 1, O32>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
+}
+
 hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t long_threshold,
                          int slot, bool has_long, int probe, bool listed, bool incremental, hipStream_t s,
                          int cus) {
@@ -697,13 +751,10 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
         }
     } else {  // probes 3 and 5 (the row lists with or without positions)
         cap = (int32_t)((blocks + kSpread - 1) / kSpread * (256 / tile_width));
-        switch (tile_width) {
-            case 4: hipLaunchKernelGGL((k_search_filter<4, 8>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
-            case 8: hipLaunchKernelGGL((k_search_filter<8, 4>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
-            case 16: hipLaunchKernelGGL((k_search_filter<16, 2>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
-            case 32: hipLaunchKernelGGL((k_search_filter<32, 1>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
-            default: return hipErrorInvalidValue;
-        }
+        const bool o32 = A.nnz < ((int64_t)1 << 30) && A.n < (1 << 28);
+        const hipError_t e = o32 ? launch_filter<true>(A, W, tile_width, blocks, long_threshold, slot, roots, cap, s)
+                                 : launch_filter<false>(A, W, tile_width, blocks, long_threshold, slot, roots, cap, s);
+        if (e != hipSuccess) return e;
     }
     if (probe >= 3) hipLaunchKernelGGL(k_search_medium, dim3(cus * 8), dim3(256), 0, s, A, W, slot, cap);
     hipError_t e = hipGetLastError();

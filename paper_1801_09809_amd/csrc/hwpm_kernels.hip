@@ -501,6 +501,16 @@ TpPlan tp_plan(int64_t n, int64_t nnz) {
     return P;
 }
 
+// Blocks go to the chip's 8 dies (XCDs, each with its own L2) in turn:
+// block b runs on die b mod 8.  This maps block b of a grid of nblk blocks
+// to a tile such that each die takes one contiguous range of tiles, in
+// order (a bijection on [0, nblk)).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t nblk) {
+    const int32_t x = b % kXcds, i = b / kXcds, q = nblk / kXcds, r = nblk % kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // The column of the first entry of every pass-1 tile: column c owns the
 // tiles whose first entry lies in [col_ptr[c], col_ptr[c+1]).
 __global__ __launch_bounds__(256) void k_tp_tile_cols(Csc A, Work W, int32_t nseg) {
@@ -685,7 +695,9 @@ __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_
     __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[MB], start[MB], base[MB];
     __shared__ int32_t wsum[NW], wmax[NW * U];
-    const int32_t seg = blockIdx.x;
+    // consecutive tiles on one die: a bucket's runs from neighbouring tiles
+    // are neighbours in memory, so their partial lines meet in one L2
+    const int32_t seg = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t k0 = (int64_t)seg * kTpTile;
     const int32_t len = (int32_t)((k0 + kTpTile < A.nnz) ? kTpTile : A.nnz - k0);
     // The column of every entry of the tile: the tile's first column, a mark

@@ -282,6 +282,31 @@ __device__ __forceinline__ int32_t tile_bcast(int32_t v, int src) {
     }
 }
 
+// OR over the tile, in every lane of the tile.  With 4-lane tiles each step
+// is one OR with a DPP quad-permuted operand.
+template <int T>
+__device__ __forceinline__ uint32_t tile_or(uint32_t v) {
+    if constexpr (T == 4) {
+        v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
+        v |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
+    } else {
+#pragma unroll
+        for (int sft = 1; sft < T; sft <<= 1) v |= (uint32_t)__shfl_xor((int32_t)v, sft, T);
+    }
+    return v;
+}
+
+// Bit T t of the result: some bit of tile t of the lane mask m is set; the
+// other bits are clear.
+template <int T>
+__device__ __forceinline__ uint64_t tile_any(uint64_t m) {
+#pragma unroll
+    for (int sft = 1; sft < T; sft <<= 1) m |= m >> sft;
+    constexpr uint64_t first = T == 4 ? 0x1111111111111111ull : T == 8 ? 0x0101010101010101ull
+                             : T == 16 ? 0x0001000100010001ull : T == 32 ? 0x0000000100000001ull : 1ull;
+    return m & first;
+}
+
 // Largest value of the tile, in every lane of the tile.
 template <int T>
 __device__ __forceinline__ int32_t tile_max(int32_t v) {
@@ -290,17 +315,20 @@ __device__ __forceinline__ int32_t tile_max(int32_t v) {
     return v;
 }
 
-// Largest value over the wave, as a wave-uniform (scalar) value: DPP row
-// shifts give every lane the maximum of its row of 16 up to itself, two row
-// broadcasts carry the rows' maxima into lane 63.  All lanes must be active.
-__device__ __forceinline__ int32_t wave_max(int32_t v) {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));  // row_shr:1
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));  // row_shr:2
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));  // row_shr:4
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));  // row_shr:8
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));  // row_bcast:15
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));  // row_bcast:31
-    return __builtin_amdgcn_readlane(v, 63);
+// Largest of non-negative values over the wave, as a wave-uniform (scalar)
+// value: DPP row shifts give every lane the maximum of its row of 16 up to
+// itself, two row broadcasts carry the rows' maxima into lane 63.  Lanes
+// without a source read 0, the identity of the unsigned maximum, so each
+// step is one maximum with a DPP operand.  All lanes must be active.
+__device__ __forceinline__ int32_t wave_max(int32_t x) {
+    uint32_t v = (uint32_t)x;
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x111, 0xF, 0xF, true));  // row_shr:1
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x112, 0xF, 0xF, true));  // row_shr:2
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x114, 0xF, 0xF, true));  // row_shr:4
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x118, 0xF, 0xF, true));  // row_shr:8
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+    return (int32_t)__builtin_amdgcn_readlane((int32_t)v, 63);
 }
 
 // Element idx of an array of at most 2^32 bytes.  With O32 the byte offset
@@ -453,7 +481,7 @@ template <int T>
 constexpr int kWideMax = T == 4 ? 2 : 0;
 
 // Steps A-C of one group of 64 / T roots (a tile per root); see below.
-template <int T, int E, bool O32>
+template <int T, int E, bool O32, bool POS>
 __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const RootView& r, int slot, int sub,
                                              int32_t cap, bool listed) {
     const int l64 = threadIdx.x & 63;
@@ -500,16 +528,8 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
         f1 |= 1ull << (h >> 26);
         f2 |= 1ull << ((h >> 20) & 63);
     }
-    uint32_t f1lo = (uint32_t)f1, f1hi = (uint32_t)(f1 >> 32), f2lo = (uint32_t)f2, f2hi = (uint32_t)(f2 >> 32);
-#pragma unroll
-    for (int sft = 1; sft < T; sft <<= 1) {
-        f1lo |= (uint32_t)tile_xor<T>((int32_t)f1lo, sft);
-        f1hi |= (uint32_t)tile_xor<T>((int32_t)f1hi, sft);
-        f2lo |= (uint32_t)tile_xor<T>((int32_t)f2lo, sft);
-        f2hi |= (uint32_t)tile_xor<T>((int32_t)f2hi, sft);
-    }
-    f1 = ((uint64_t)f1hi << 32) | f1lo;
-    f2 = ((uint64_t)f2hi << 32) | f2lo;
+    f1 = ((uint64_t)tile_or<T>((uint32_t)(f1 >> 32)) << 32) | tile_or<T>((uint32_t)f1);
+    f2 = ((uint64_t)tile_or<T>((uint32_t)(f2 >> 32)) << 32) | tile_or<T>((uint32_t)f2);
     // the probes against it; a lane's own probes are its first nm entries
     const int32_t nm = search && r.slen > lane ? (r.slen - lane + T - 1) / T : 0;
     uint32_t pending = 0;  // bit e: probe e passed the filter
@@ -528,6 +548,27 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
 #pragma unroll
         for (int u = 0; u < E; ++u)
             if (u == e) mi = mv[u];
+        if constexpr (!POS) {
+            // membership only (the closing edge is then found in column m_i):
+            // the tile's probes, each compared by every lane with its own part
+            // of the row list into one lane mask per probe; bit T t + src of
+            // `held` says whether tile t holds the probe of its lane src
+            uint64_t held = 0;
+#pragma unroll
+            for (int src = 0; src < T; ++src) {
+                const int32_t ps = tile_bcast<T>(mi, src);
+                uint64_t m = 0;
+#pragma unroll
+                for (int f = 0; f < E; ++f) m |= __ballot(rv[f] == ps);
+                held |= tile_any<T>(m) << src;
+            }
+            if ((held >> l64) & 1u) {
+                const int32_t k = r.s0 + lane + T * e;
+                const int64_t p = find_row(A.col_ptr, A.row_idx, mi, W.mc[r.j]);
+                if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[r.j]), k, mi, p);
+            }
+            continue;
+        }
         // the tile's probes, each compared by every lane with its own part
         // of the row list; the matching place comes back to the probe's lane
         // (a match with a repeat of the list's last entry lies past the
@@ -546,7 +587,7 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
         if (q >= 0) {
             q = min(q, r.rl.y - 1);
             const int32_t k = r.s0 + lane + T * e;
-            const int64_t p = W.cscpos ? (int64_t)W.cscpos[r.rl.x + q] : find_row(A.col_ptr, A.row_idx, mi, W.mc[r.j]);
+            const int64_t p = W.cscpos[r.rl.x + q];
             if (p >= 0) offer(b, (A.w[k] + A.w[p]) - (W.wm[mi] + W.wm[r.j]), k, mi, p);
         }
     }
@@ -558,8 +599,9 @@ __device__ __forceinline__ void search_group(const Csc& A, const Work& W, const 
 }
 
 // One group of 64 / T roots per wave.  O32: every array the tiles index holds
-// at most 2^32 bytes (nnz < 2^30, n < 2^28).
-template <int T, int E, bool O32>
+// at most 2^32 bytes (nnz < 2^30, n < 2^28).  POS: the row lists carry the
+// CSC positions of their entries.
+template <int T, int E, bool O32, bool POS>
 __global__ __launch_bounds__(256, 8) void k_search_filter(Csc A, Work W, int32_t long_threshold, int slot,
                                                           const int32_t* __restrict__ roots, int32_t cap) {
     constexpr int kTiles = 64 / T;
@@ -568,7 +610,7 @@ __global__ __launch_bounds__(256, 8) void k_search_filter(Csc A, Work W, int32_t
     const int64_t grp = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     if (grp * kTiles >= ntiles) return;  // wave-uniform
     const RootView r = load_root<O32>(W, grp * kTiles + (threadIdx.x & 63) / T, ntiles, roots, long_threshold);
-    search_group<T, E, O32>(A, W, r, slot, (int)(blockIdx.x & (kSpread - 1)), cap, roots != nullptr);
+    search_group<T, E, O32, POS>(A, W, r, slot, (int)(blockIdx.x & (kSpread - 1)), cap, roots != nullptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -698,14 +740,14 @@ __global__ __launch_bounds__(256) void k_search_medium(Csc A, Work W, int slot, 
     }
 }
 
-template <bool O32>
+template <bool O32, bool POS>
 static hipError_t launch_filter(const Csc& A, const Work& W, int tile_width, unsigned blocks, int32_t long_threshold,
                                 int slot, const int32_t* roots, int32_t cap, hipStream_t s) {
     switch (tile_width) {
-        case 4: hipLaunchKernelGGL((k_search_filter<4, 8, O32>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
-        case 8: hipLaunchKernelGGL((k_search_filter<8, 4, O32>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
-        case 16: hipLaunchKernelGGL((k_search_filter<16, 2, O32>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
-        case 32: hipLaunchKernelGGL((k_search_filter<32, 1, O32>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+        case 4: hipLaunchKernelGGL((k_search_filter<4, 8, O32, POS>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+        case 8: hipLaunchKernelGGL((k_search_filter<8, 4, O32, POS>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+        case 16: hipLaunchKernelGGL((k_search_filter<16, 2, O32, POS>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
+        case 32: hipLaunchKernelGGL((k_search_filter<32, 1, O32, POS>), dim3(blocks), dim3(256), 0, s, A, W, long_threshold, slot, roots, cap); break;
         default: return hipErrorInvalidValue;
     }
     return hipSuccess;
@@ -752,8 +794,12 @@ hipError_t launch_search(const Csc& A, const Work& W, int tile_width, int32_t lo
     } else {  // probes 3 and 5 (the row lists with or without positions)
         cap = (int32_t)((blocks + kSpread - 1) / kSpread * (256 / tile_width));
         const bool o32 = A.nnz < ((int64_t)1 << 30) && A.n < (1 << 28);
-        const hipError_t e = o32 ? launch_filter<true>(A, W, tile_width, blocks, long_threshold, slot, roots, cap, s)
-                                 : launch_filter<false>(A, W, tile_width, blocks, long_threshold, slot, roots, cap, s);
+        const bool pos = W.cscpos != nullptr;
+        const hipError_t e =
+            o32 ? (pos ? launch_filter<true, true>(A, W, tile_width, blocks, long_threshold, slot, roots, cap, s)
+                       : launch_filter<true, false>(A, W, tile_width, blocks, long_threshold, slot, roots, cap, s))
+                : (pos ? launch_filter<false, true>(A, W, tile_width, blocks, long_threshold, slot, roots, cap, s)
+                       : launch_filter<false, false>(A, W, tile_width, blocks, long_threshold, slot, roots, cap, s));
         if (e != hipSuccess) return e;
     }
     if (probe >= 3) hipLaunchKernelGGL(k_search_medium, dim3(cus * 8), dim3(256), 0, s, A, W, slot, cap);

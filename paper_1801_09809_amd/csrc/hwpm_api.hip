@@ -25,6 +25,9 @@ struct hwpm_handle_s {
     // 0-7: stage events; 8 + 4*b .. 8 + 4*b + 3: the stages of the b-th
     // round of a batch of queued rounds
     hipEvent_t ev[8 + 8 * kSlots];  // 8 stage events, two sets of 4 per round of a batch
+    // the set-up readback done (with the system-scope release, so the host
+    // may read what the copies before it wrote) while later work still runs
+    hipEvent_t ready;
 };
 
 namespace {
@@ -180,7 +183,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     if (probe >= 2 && A.nnz >= ((int64_t)1 << 31)) probe = 1;
     // probe 5: the chunked kernels over row lists built without CSC positions
     // (a hit or a mate refresh searches its entry's position instead)
-    const bool light = probe == 5 && transpose_without_positions(A.n, A.nnz);
+    const bool light = probe == 5 && transpose_in_buckets(A.n, A.nnz);
     if (probe == 5) probe = 3;
     S.probe_used = light ? 5 : probe;
     S.tile_used = tile;
@@ -197,7 +200,21 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     HIP_TRY(hipMemcpyAsync(h->host, W.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[1], sizeof(double), hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[1], s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // The bucket transpose needs nothing the host reads back here: it is
+    // queued before the wait, so the device goes on while the host checks
+    // the matching (its kernels return at once if the check failed).  The
+    // slots of long row lists' hash tables are noted whatever the columns;
+    // the tables are filled below only if the rounds use them.
+    const bool early = transposed && transpose_in_buckets(n, A.nnz);
+    if (early) {
+        HIP_TRY(hipEventRecord(h->ready, s));
+        if (timing) HIP_TRY(hipEventRecord(ev[2], s));
+        if (incremental) HIP_TRY(hipMemsetAsync(W.dirty, 0, (size_t)n * sizeof(int32_t), s));
+        HIP_TRY(launch_transpose_buckets(A, W, !light, s, h->cus));
+        HIP_TRY(hipEventSynchronize(h->ready));
+    } else {
+        HIP_TRY(hipStreamSynchronize(s));
+    }
     if (h->host[kErrMatch]) return HWPM_EBADMATCH;
     if (BP) HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_init, s, h->cus));
     const int32_t n_long = h->host[kNumLong];
@@ -208,7 +225,10 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     if (n_long > 0) HIP_TRY(launch_long_chunks(W, A, s));
     S.long_columns = n_long;
     memcpy(&S.init_weight, h->host + kHostScalar, sizeof(double));
-    if (transposed) {
+    if (early) {
+        HIP_TRY(launch_rowsets(A, Wr, s, h->cus));
+        if (timing) HIP_TRY(hipEventRecord(ev[3], s));  // read at the end
+    } else if (transposed) {
         if (timing) HIP_TRY(hipEventRecord(ev[2], s));
         if (incremental) HIP_TRY(hipMemsetAsync(W.dirty, 0, (size_t)n * sizeof(int32_t), s));
         Work Wt = W;
@@ -689,8 +709,11 @@ int hwpm_create(hwpm_handle* out, int device, void* stream) {
         ok = hipEventCreateWithFlags(&h->ev[ne], hipEventDisableSystemFence) == hipSuccess;
         if (ok) ++ne;
     }
+    h->ready = nullptr;
+    ok = ok && hipEventCreateWithFlags(&h->ready, hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         for (int e = 0; e < ne; ++e) (void)hipEventDestroy(h->ev[e]);
+        if (h->ready) (void)hipEventDestroy(h->ready);
         if (h->host) (void)hipHostFree(h->host);
         if (h->cap) (void)hipStreamDestroy(h->cap);
         delete h;
@@ -705,6 +728,7 @@ int hwpm_destroy(hwpm_handle h) {
     DeviceGuard g(h->device);
     (void)hipStreamSynchronize(h->stream);
     for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+    (void)hipEventDestroy(h->ready);
     (void)hipHostFree(h->host);
     (void)hipStreamDestroy(h->cap);
     delete h;

@@ -239,7 +239,13 @@ hipError_t launch_round_end(const Work& W, int slot, bool listed, int32_t n, hip
 hipError_t launch_collect(const Csc& A, const Work& W, int slot, hipStream_t s, int cus);
 hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
                             bool positions, hipStream_t s, int cus);
-bool transpose_without_positions(int64_t n, int64_t nnz);
+// The bucket transpose (it also fills mrk) works for this size; it is the
+// one that can go without positions.  launch_transpose_buckets queues it
+// without the long lists' hash tables, which launch_rowsets fills (when
+// W.rtab is set).  Its kernels return at once if the matching check failed.
+bool transpose_in_buckets(int64_t n, int64_t nnz);
+hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions, hipStream_t s, int cus);
+hipError_t launch_rowsets(const Csc& A, const Work& W, hipStream_t s, int cus);
 hipError_t launch_mrk_update(const Csc& A, const Work& W, int slot, bool incremental, hipStream_t s, int cus);
 hipError_t launch_resolve(const Work& W, int slot, hipStream_t s, int cus);
 hipError_t launch_apply(const Csc& A, const Work& W, int slot, bool transposed, hipStream_t s,

@@ -67,13 +67,16 @@ hipError_t launch_check_csc(const Csc& A, const Work& W, hipStream_t s, int cus)
 // Algorithm 2), validate the matching, list the long columns.
 
 // find_row, given the column's bounds, with the final window's nine reads
-// issued together: each index
-// is clamped to the column's last entry (to entry 0 for an empty column, so
-// the matrix must hold at least one entry) and only the slots inside the
-// column can hit.  One thread per column here, so the nine registers are
-// cheap; the search kernels keep find_row.
+// issued together.  VEC (at least nine entries in the matrix): the window is
+// read as two 16-byte loads and one 4-byte load from its start, moved back
+// to keep inside the array (one thread per column, neighbouring lanes about
+// a column apart, so each load instruction is one request per lane).
+// Otherwise each index is clamped to the column's last entry (to entry 0 for
+// an empty column, so the matrix must hold at least one entry).  Only the
+// slots inside the column can hit.  The search kernels keep find_row.
+template <bool VEC>
 __device__ __forceinline__ int64_t find_row_window(const int32_t* __restrict__ row_idx, int64_t lo,
-                                                   int64_t end, int32_t r) {
+                                                   int64_t end, int32_t r, int64_t nnz) {
     // the column is row_idx[lo, end)
     int64_t len = end - lo;
     while (len > 8) {
@@ -86,20 +89,33 @@ __device__ __forceinline__ int64_t find_row_window(const int32_t* __restrict__ r
         }
     }
     int32_t v[9];
-#pragma unroll
-    for (int q = 0; q <= 8; ++q) {
-        const int64_t pos = lo + q;
-        v[q] = row_idx[pos < end ? pos : (end > 0 ? end - 1 : 0)];
-    }
     int64_t hit = -1;
+    if constexpr (VEC) {
+        const int64_t base = lo + 9 <= nnz ? lo : nnz - 9;  // <= lo
+        __builtin_memcpy(v, row_idx + base, 16);
+        __builtin_memcpy(v + 4, row_idx + base + 4, 16);
+        v[8] = row_idx[base + 8];
 #pragma unroll
-    for (int q = 0; q <= 8; ++q)
-        if (q <= len && lo + q < end && v[q] == r) hit = lo + q;
+        for (int q = 0; q <= 8; ++q) {
+            const int64_t pos = base + q;
+            if (pos >= lo && pos <= lo + len && pos < end && v[q] == r) hit = pos;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q <= 8; ++q) {
+            const int64_t pos = lo + q;
+            v[q] = row_idx[pos < end ? pos : (end > 0 ? end - 1 : 0)];
+        }
+#pragma unroll
+        for (int q = 0; q <= 8; ++q)
+            if (q <= len && lo + q < end && v[q] == r) hit = lo + q;
+    }
     return hit;
 }
 
 // With pos32 (nnz < 2^31) it also fills the 32-bit column pointers and the
 // matched positions the transposed searches read.
+template <bool VEC>
 __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
                              int32_t long_threshold, int pos32) {
     for (int64_t jj = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; jj < A.n;
@@ -126,7 +142,7 @@ __global__ void k_init_match(Csc A, Work W, const int32_t* __restrict__ mate_in,
         }
         W.mr[r] = j;  // a row claimed twice keeps one writer: k_check_match sees the other
         W.mc[j] = r;
-        const int64_t p = find_row_window(A.row_idx, lo, hi, r);
+        const int64_t p = find_row_window<VEC>(A.row_idx, lo, hi, r, A.nnz);
         if (p < 0) {
             atomicOr(&W.counters[kErrMatch], 4);
             W.wm[j] = 0.0;
@@ -152,7 +168,10 @@ hipError_t launch_init_match(const Csc& A, const Work& W, const int32_t* mate_in
     const int64_t blocks = ((int64_t)A.n + 255) / 256;
     const unsigned g = (unsigned)(blocks < 65536 ? blocks : 65536);
     const int pos32 = A.nnz < ((int64_t)1 << 31) ? 1 : 0;
-    hipLaunchKernelGGL(k_init_match, dim3(g), dim3(256), 0, s, A, W, mate_in, long_threshold, pos32);
+    if (A.nnz >= 9)
+        hipLaunchKernelGGL(k_init_match<true>, dim3(g), dim3(256), 0, s, A, W, mate_in, long_threshold, pos32);
+    else
+        hipLaunchKernelGGL(k_init_match<false>, dim3(g), dim3(256), 0, s, A, W, mate_in, long_threshold, pos32);
     hipLaunchKernelGGL(k_check_match, dim3(g), dim3(256), 0, s, A, W);
     return hipGetLastError();
 }
@@ -547,6 +566,7 @@ __global__ __launch_bounds__(256) void k_tp_hist(Csc A, Work W, int rb, int32_t 
                                                  int32_t* __restrict__ cnt) {
     constexpr int U = kTpTile / 256;
     __shared__ int32_t hist[kTpMaxBuckets];
+    if (W.counters[kErrMatch]) return;  // block-uniform: no slots without a matching
     for (int b = threadIdx.x; b < nb; b += blockDim.x) hist[b] = 0;
     __syncthreads();
     const int32_t seg = blockIdx.x;
@@ -695,6 +715,7 @@ __global__ __launch_bounds__(NT) void k_tp_scatter(Csc A, Work W, int rb, int32_
     __shared__ int32_t s_slot[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[MB], start[MB], base[MB];
     __shared__ int32_t wsum[NW], wmax[NW * U];
+    if (W.counters[kErrMatch]) return;  // block-uniform: no slots without a matching
     // consecutive tiles on one die: a bucket's runs from neighbouring tiles
     // are neighbours in memory, so their partial lines meet in one L2
     const int32_t seg = xcd_tile(blockIdx.x, gridDim.x);
@@ -803,6 +824,7 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
                                                    const int64_t* __restrict__ bstart) {
     __shared__ int32_t s_slot[kTpTile], s_col[PACK ? 1 : kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[kTpSub], start[kTpSub], cursor[kTpSub];
+    if (W.counters[kErrMatch]) return;  // block-uniform: no slots without a matching
     const int32_t b = blockIdx.x;
     const int64_t r0 = (int64_t)b << rb;
     const int sb = rb - 6;
@@ -904,6 +926,7 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     constexpr int U = kPlaceTile / 256;
     __shared__ int32_t rc[NS], tc[NS], ts[NS];
     __shared__ int32_t s_key[kPlaceTile], s_col[kPlaceTile], s_pos[POS ? kPlaceTile : 1];
+    if (W.counters[kErrMatch]) return;  // block-uniform: no slots without a matching
     const int32_t g = blockIdx.x;
     const int32_t b = g / kTpSub, sub = g % kTpSub;
     const int sb = rb - 6;
@@ -1100,7 +1123,7 @@ hipError_t launch_rowsets(const Csc& A, const Work& W, hipStream_t s, int cus) {
     return hipGetLastError();
 }
 
-bool transpose_without_positions(int64_t n, int64_t nnz) { return tp_plan(n, nnz).ok; }
+bool transpose_in_buckets(int64_t n, int64_t nnz) { return tp_plan(n, nnz).ok; }
 
 hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
                             bool positions, hipStream_t s, int cus) {

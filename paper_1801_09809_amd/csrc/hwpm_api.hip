@@ -35,12 +35,28 @@ namespace {
 constexpr int kDefaultTile = 4;
 constexpr int kDefaultProbe = 3;
 constexpr int32_t kLongThreshold = 256;   // longer columns use the split search
-// int32 index of the 8-byte scalar readback slot in the pinned host buffer
-// (after the two ring slots of per-round words)
-constexpr int kHostScalar = 64;
-// int32 index of the per-round statistics (3 x kMaxRoundStats words)
-constexpr int kHostRounds = 256;
-constexpr size_t kHostBytes = (kHostRounds + 3 * kMaxRoundStats) * sizeof(int32_t);
+// The report of a run is one range of the workspace, read back with one
+// copy into the pinned buffer at int32 index kHostReport: the results
+// (W.result), the per-round statistics (W.round_stats) and the first
+// kReportCounters counter words (the workspace lays them out in that order).
+constexpr int kReportCounters = 8;
+static_assert(kErrMatch < kReportCounters && kNumLong < kReportCounters && kCycles + 2 <= kReportCounters,
+              "report counter words");
+constexpr int kHostReport = 64;
+constexpr size_t kReportMaxBytes = 256 + 3 * kMaxRoundStats * sizeof(int32_t) + 256;
+constexpr size_t kHostBytes = kHostReport * sizeof(int32_t) + kReportMaxBytes;
+
+// Where the report's parts sit, in bytes from W.result.
+struct Report {
+    size_t stats, counters, bytes;  // bytes: up to the end of the counter words read
+};
+Report report_of(const Work& W) {
+    Report r;
+    r.stats = (size_t)((const char*)W.round_stats - (const char*)W.result);
+    r.counters = (size_t)((const char*)W.counters - (const char*)W.result);
+    r.bytes = r.counters + kReportCounters * sizeof(int32_t);
+    return r;
+}
 constexpr int64_t kMaxNnz = (int64_t)1 << 40;
 
 // The workspace of hwpm_improve_static: a fixed device array, one copy per
@@ -194,11 +210,15 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     // 2. set-up: mates, matched weights, matching validation, long columns
     if (timing) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(hipMemsetAsync(W.counters, 0, kCounterWords * sizeof(int32_t), s));
-    HIP_TRY(hipMemsetAsync(W.mr, 0xff, (size_t)n * sizeof(int32_t), s));
     HIP_TRY(launch_init_match(A, W, mate_in, kLongThreshold, s));
     HIP_TRY(launch_tree_sum(W.wm, n, W, &W.result[1], s));
-    HIP_TRY(hipMemcpyAsync(h->host, W.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[1], sizeof(double), hipMemcpyDeviceToHost, s));
+    const Report rep = report_of(W);
+    if (rep.stats < 4 * sizeof(double) || rep.counters < rep.stats + 3 * kMaxRoundStats * sizeof(int32_t) ||
+        rep.bytes > kReportMaxBytes)
+        return HWPM_EINTERNAL;
+    char* const rhost = (char*)(h->host + kHostReport);
+    const int32_t* const rcount = (const int32_t*)(rhost + rep.counters);
+    HIP_TRY(hipMemcpyAsync(rhost, W.result, rep.bytes, hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[1], s));
     // The bucket transpose needs nothing the host reads back here: it is
     // queued before the wait, so the device goes on while the host checks
@@ -215,16 +235,16 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     } else {
         HIP_TRY(hipStreamSynchronize(s));
     }
-    if (h->host[kErrMatch]) return HWPM_EBADMATCH;
+    if (rcount[kErrMatch]) return HWPM_EBADMATCH;
     if (BP) HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_init, s, h->cus));
-    const int32_t n_long = h->host[kNumLong];
+    const int32_t n_long = rcount[kNumLong];
     // hash tables of the long row lists only for matrices with long columns
     // (where long row lists occur on real patterns); elsewhere the rounds see
     // no tables and the pass that fills them is not launched
     if (n_long == 0) Wr.rtab = nullptr;
     if (n_long > 0) HIP_TRY(launch_long_chunks(W, A, s));
     S.long_columns = n_long;
-    memcpy(&S.init_weight, h->host + kHostScalar, sizeof(double));
+    memcpy(&S.init_weight, rhost + sizeof(double), sizeof(double));
     if (early) {
         HIP_TRY(launch_rowsets(A, Wr, s, h->cus));
         if (timing) HIP_TRY(hipEventRecord(ev[3], s));  // read at the end
@@ -278,10 +298,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
             HIP_TRY(launch_seg_tree(*BP, W.wm, BP->item_total, s, h->cus));
             HIP_TRY(launch_unpack(*BP, W.mc, s, h->cus));
         }
-        HIP_TRY(hipMemcpyAsync(h->host + kHostScalar, &W.result[0], sizeof(double), hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(h->host + kHostRounds, W.round_stats, 3 * kMaxRoundStats * sizeof(int32_t),
-                               hipMemcpyDeviceToHost, s));
-        HIP_TRY(hipMemcpyAsync(h->host + kHostScalar + 2, W.counters + kCycles, 8, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(rhost, W.result, rep.bytes, hipMemcpyDeviceToHost, s));
         if (timing) HIP_TRY(hipEventRecord(ev[7], s));
         return HWPM_OK;
     };
@@ -363,15 +380,16 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
         S.ms_final = elapsed(ev[6], ev[7]);
     }
     unsigned long long cycles = 0;
-    memcpy(&cycles, h->host + kHostScalar + 2, sizeof(cycles));
+    memcpy(&cycles, rcount + kCycles, sizeof(cycles));
     S.cycles_applied = (int64_t)cycles;
     if (n_stats > 0) {
-        memcpy(S.round_candidates, h->host + kHostRounds, (size_t)n_stats * sizeof(int32_t));
-        memcpy(S.round_applied, h->host + kHostRounds + kMaxRoundStats, (size_t)n_stats * sizeof(int32_t));
-        memcpy(S.round_roots, h->host + kHostRounds + 2 * kMaxRoundStats, (size_t)n_stats * sizeof(int32_t));
+        const int32_t* st = (const int32_t*)(rhost + rep.stats);
+        memcpy(S.round_candidates, st, (size_t)n_stats * sizeof(int32_t));
+        memcpy(S.round_applied, st + kMaxRoundStats, (size_t)n_stats * sizeof(int32_t));
+        memcpy(S.round_roots, st + 2 * kMaxRoundStats, (size_t)n_stats * sizeof(int32_t));
     }
     double total;
-    memcpy(&total, h->host + kHostScalar, sizeof(double));
+    memcpy(&total, rhost, sizeof(double));
     S.final_weight = total;
     *total_out = total;
     return HWPM_OK;

@@ -1367,8 +1367,11 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.tree_a = (double*)take(tree1 * 8);
     W.tree_b = (double*)take(tree1 * 8);
     W.bitmap = (uint32_t*)take((Z + 1) / 32 * 4 + 8);
-    W.counters = (int32_t*)take(kCounterWords * 4);
+    // the run's report, read back as one range: result, per-round
+    // statistics, then the counters (whose first words are the scalars)
     W.result = (double*)take(4 * 8);
+    W.round_stats = (int32_t*)take(3 * kMaxRoundStats * 4);
+    W.counters = (int32_t*)take(kCounterWords * 4);
     W.max_chunks = (int64_t)max_chunks;
     W.rowptr = (int64_t*)take((N + 1) * 8);
     W.rsl = (int2*)take(N * 8);
@@ -1386,7 +1389,6 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.dirty_list = (int32_t*)take(N * 4);
     W.medium = (int32_t*)take((N + kSpread * 64) * 4);
     W.heavy = (int32_t*)take(N * 4);
-    W.round_stats = (int32_t*)take(3 * kMaxRoundStats * 4);
     const TpPlan P = tp_plan(n, nnz);
     const size_t tpm = P.ok ? (size_t)(P.nb * P.nseg) : 0;
     const size_t tpz = P.ok ? Z : 0;

@@ -220,11 +220,13 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     const int32_t* const rcount = (const int32_t*)(rhost + rep.counters);
     HIP_TRY(hipMemcpyAsync(rhost, W.result, rep.bytes, hipMemcpyDeviceToHost, s));
     if (timing) HIP_TRY(hipEventRecord(ev[1], s));
-    // The bucket transpose needs nothing the host reads back here: it is
-    // queued before the wait, so the device goes on while the host checks
-    // the matching (its kernels return at once if the check failed).  The
-    // slots of long row lists' hash tables are noted whatever the columns;
-    // the tables are filled below only if the rounds use them.
+    // The bucket transpose's first pass needs nothing the host reads back
+    // here: it is queued before the wait, so the device goes on while the
+    // host checks the matching (its kernels return at once if the check
+    // failed).  The rest follows, with the split of oversized buckets over
+    // the grid on matrices with long columns (skewed ones); the slots of
+    // long row lists' hash tables are noted whatever the columns, and the
+    // tables are filled only if the rounds use them.
     const bool early = transposed && transpose_in_buckets(n, A.nnz);
     if (early) {
         HIP_TRY(hipEventRecord(h->ready, s));
@@ -246,6 +248,7 @@ int run_improve(hwpm_handle h, const Csc& A, const Work& W, const int32_t* mate_
     S.long_columns = n_long;
     memcpy(&S.init_weight, rhost + sizeof(double), sizeof(double));
     if (early) {
+        HIP_TRY(launch_transpose_rest(A, W, !light, n_long > 0, s, h->cus));
         HIP_TRY(launch_rowsets(A, Wr, s, h->cus));
         if (timing) HIP_TRY(hipEventRecord(ev[3], s));  // read at the end
     } else if (transposed) {

@@ -145,6 +145,7 @@ struct Work {
     int32_t* tp_col2;
     int32_t* tp_pos2;
     int64_t* tp_sub;    // start of every sub-bucket (+ total)
+    int32_t* tp_bigcnt; // oversized buckets: kTpSub counts, then places, per tile
     // batched solves (nullptr otherwise): the block of every packed column and
     // per-block flip flags / counts
     const int32_t* mat_of_col;
@@ -240,11 +241,14 @@ hipError_t launch_collect(const Csc& A, const Work& W, int slot, hipStream_t s, 
 hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold, bool has_long,
                             bool positions, hipStream_t s, int cus);
 // The bucket transpose (it also fills mrk) works for this size; it is the
-// one that can go without positions.  launch_transpose_buckets queues it
-// without the long lists' hash tables, which launch_rowsets fills (when
-// W.rtab is set).  Its kernels return at once if the matching check failed.
+// one that can go without positions.  launch_transpose_buckets queues its
+// first pass (up to the bucket scatter), launch_transpose_rest the others
+// (with big, oversized buckets are split by the whole grid); the long
+// lists' hash tables are filled by launch_rowsets (when W.rtab is set).
+// Its kernels return at once if the matching check failed.
 bool transpose_in_buckets(int64_t n, int64_t nnz);
 hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions, hipStream_t s, int cus);
+hipError_t launch_transpose_rest(const Csc& A, const Work& W, bool positions, bool big, hipStream_t s, int cus);
 hipError_t launch_rowsets(const Csc& A, const Work& W, hipStream_t s, int cus);
 hipError_t launch_mrk_update(const Csc& A, const Work& W, int slot, bool incremental, hipStream_t s, int cus);
 hipError_t launch_resolve(const Work& W, int slot, hipStream_t s, int cus);

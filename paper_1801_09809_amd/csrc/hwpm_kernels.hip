@@ -821,7 +821,7 @@ constexpr int kTpSub = 64;
 
 template <bool POS, bool PACK>
 __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_t nb,
-                                                   const int64_t* __restrict__ bstart) {
+                                                   const int64_t* __restrict__ bstart, int64_t big_min) {
     __shared__ int32_t s_slot[kTpTile], s_col[PACK ? 1 : kTpTile], s_pos[POS ? kTpTile : 1];
     __shared__ int32_t hist[kTpSub], start[kTpSub], cursor[kTpSub];
     if (W.counters[kErrMatch]) return;  // block-uniform: no slots without a matching
@@ -830,6 +830,8 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
     const int sb = rb - 6;
     const int64_t e0 = bstart[b], e1 = bstart[b + 1];
     const int t = threadIdx.x;
+    if (b == nb - 1 && t == 0) W.tp_sub[(int64_t)nb * kTpSub] = A.nnz;
+    if (e1 - e0 > big_min) return;  // an oversized bucket: the grid-wide split takes it
     if (t < kTpSub) hist[t] = 0;
     __syncthreads();
     // loads first (four per thread, indices clamped into the bucket), then
@@ -857,7 +859,6 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
         }
         cursor[t] = incl - v;  // relative to e0
         W.tp_sub[(int64_t)b * kTpSub + t] = e0 + incl - v;
-        if (b == nb - 1 && t == 63) W.tp_sub[(int64_t)nb * kTpSub] = A.nnz;
     }
     __syncthreads();
     for (int64_t t0 = e0; t0 < e1; t0 += kTpTile) {
@@ -909,6 +910,211 @@ __global__ __launch_bounds__(1024) void k_tp_split(Csc A, Work W, int rb, int32_
         }
         __syncthreads();
         if (t < kTpSub) cursor[t] += hist[t];
+        __syncthreads();
+    }
+}
+
+// Pass 2 for oversized buckets (more than big_min entries; on skewed
+// matrices one bucket can hold a large share of all entries, which one block
+// would work through alone): the same split, spread over the whole grid.
+// The oversized buckets' entries are cut into kTpTile-entry tiles, numbered
+// bucket by bucket; each tile's sub-bucket counts go to a table (a row of
+// kTpSub counts per tile), a block per bucket scans the table's columns into
+// each tile's place in each sub-bucket, and the tiles are then sorted by
+// sub-bucket in LDS and written in runs, as in pass 1.
+
+// The oversized buckets in order, and the number of the first tile of each
+// (vt[k], with vt[nbig] the total), built in LDS by every block of NT
+// threads (wsum: 2 NT / 64 words); returns nbig.
+template <int NT>
+__device__ int32_t big_buckets(const int64_t* __restrict__ bstart, int32_t nb, int64_t big_min, int32_t* bk,
+                               int32_t* vt, int32_t* wsum) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int PER = kTpMaxBuckets / NT;
+    int32_t nbig = 0, ntile = 0;
+    int32_t flag[PER], tiles[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int32_t b = t * PER + u;
+        const int64_t len = b < nb ? bstart[b + 1] - bstart[b] : 0;
+        flag[u] = len > big_min ? 1 : 0;
+        tiles[u] = flag[u] ? (int32_t)((len + kTpTile - 1) / kTpTile) : 0;
+        nbig += flag[u];
+        ntile += tiles[u];
+    }
+    // exclusive scans of (nbig, ntile) over the block, packed as one 64-bit value
+    int64_t v = ((int64_t)nbig << 32) | (uint32_t)ntile, incl = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t x = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += x;
+    }
+    if (lane == 63) {
+        wsum[2 * wave] = (int32_t)(incl >> 32);
+        wsum[2 * wave + 1] = (int32_t)incl;
+    }
+    __syncthreads();
+    int64_t pre = incl - v;
+    for (int w = 0; w < wave; ++w) pre += ((int64_t)wsum[2 * w] << 32) + wsum[2 * w + 1];
+    int32_t kb = (int32_t)(pre >> 32), kt = (int32_t)pre;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        if (flag[u]) {
+            bk[kb] = t * PER + u;
+            vt[kb] = kt;
+            ++kb;
+            kt += tiles[u];
+        }
+    }
+    int32_t total_b = 0, total_t = 0;
+    for (int w = 0; w < NT / 64; ++w) {
+        total_b += wsum[2 * w];
+        total_t += wsum[2 * w + 1];
+    }
+    if (t == 0) vt[total_b] = total_t;
+    __syncthreads();
+    return total_b;
+}
+
+// The oversized bucket and the entry range of tile x of the numbering.
+__device__ __forceinline__ void big_tile(const int32_t* bk, const int32_t* vt, int32_t nbig, int32_t x,
+                                         const int64_t* __restrict__ bstart, int32_t* b, int64_t* e0,
+                                         int64_t* e1) {
+    int32_t lo = 0, hi = nbig - 1;  // the last k with vt[k] <= x
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (vt[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    *b = bk[lo];
+    const int64_t s0 = bstart[*b] + (int64_t)(x - vt[lo]) * kTpTile, end = bstart[*b + 1];
+    *e0 = s0;
+    *e1 = s0 + kTpTile < end ? s0 + kTpTile : end;
+}
+
+template <bool PACK>
+__global__ __launch_bounds__(256) void k_tp_big_count(Work W, int rb, int32_t nb, const int64_t* __restrict__ bstart,
+                                                      int64_t big_min, int32_t* __restrict__ cnt) {
+    __shared__ int32_t bk[kTpMaxBuckets], vt[kTpMaxBuckets + 1], wsum[8], hist[kTpSub];
+    const int32_t nbig = big_buckets<256>(bstart, nb, big_min, bk, vt, wsum);
+    const int sb = rb - 6, t = threadIdx.x;
+    for (int32_t x = blockIdx.x; x < vt[nbig]; x += gridDim.x) {
+        int32_t b;
+        int64_t e0, e1;
+        big_tile(bk, vt, nbig, x, bstart, &b, &e0, &e1);
+        if (t < kTpSub) hist[t] = 0;
+        __syncthreads();
+        const int32_t r0 = b << rb;
+        for (int64_t e = e0 + t; e < e1; e += 256) {
+            const int32_t wd = W.tp_row[e];
+            atomicAdd(&hist[(PACK ? tp_local(wd, rb) : wd - r0) >> sb], 1);
+        }
+        __syncthreads();
+        if (t < kTpSub) cnt[(int64_t)x * kTpSub + t] = hist[t];
+        __syncthreads();
+    }
+}
+
+// One block per oversized bucket: 16 parts of its tiles per sub-bucket.
+// Each count becomes the place of that tile's run in its bucket.
+__global__ __launch_bounds__(1024) void k_tp_big_scan(Work W, int32_t nb, const int64_t* __restrict__ bstart,
+                                                      int64_t big_min, int32_t* __restrict__ cnt) {
+    __shared__ int32_t bk[kTpMaxBuckets], vt[kTpMaxBuckets + 1], wsum[32];
+    __shared__ int32_t part[16][kTpSub];
+    const int32_t nbig = big_buckets<1024>(bstart, nb, big_min, bk, vt, wsum);
+    const int t = threadIdx.x, sub = t & 63, pt = t >> 6;
+    for (int32_t k = blockIdx.x; k < nbig; k += gridDim.x) {
+        const int32_t b = bk[k], x0 = vt[k], nt = vt[k + 1] - vt[k];
+        const int32_t per = (nt + 15) / 16;
+        const int32_t xa = x0 + (pt * per < nt ? pt * per : nt), xb = x0 + ((pt + 1) * per < nt ? (pt + 1) * per : nt);
+        int32_t run = 0;
+        for (int32_t x = xa; x < xb; ++x) run += cnt[(int64_t)x * kTpSub + sub];
+        part[pt][sub] = run;
+        __syncthreads();
+        if (t < 64) {  // prefix over the parts, then over the sub-buckets
+            int32_t acc = 0;
+            for (int p = 0; p < 16; ++p) {
+                const int32_t c = part[p][t];
+                part[p][t] = acc;
+                acc += c;
+            }
+            int32_t incl = acc;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t y = __shfl_up(incl, o, 64);
+                if (t >= o) incl += y;
+            }
+            const int32_t st = incl - acc;
+            W.tp_sub[(int64_t)b * kTpSub + t] = bstart[b] + st;
+            for (int p = 0; p < 16; ++p) part[p][t] += st;
+        }
+        __syncthreads();
+        run = part[pt][sub];
+        for (int32_t x = xa; x < xb; ++x) {
+            const int32_t c = cnt[(int64_t)x * kTpSub + sub];
+            cnt[(int64_t)x * kTpSub + sub] = run;
+            run += c;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool POS, bool PACK>
+__global__ __launch_bounds__(1024) void k_tp_big_scatter(Csc A, Work W, int rb, int32_t nb,
+                                                         const int64_t* __restrict__ bstart, int64_t big_min,
+                                                         const int32_t* __restrict__ cnt) {
+    __shared__ int32_t bk[kTpMaxBuckets], vt[kTpMaxBuckets + 1], wsum[32];
+    __shared__ int32_t s_slot[kTpTile], s_col[PACK ? 1 : kTpTile], s_pos[POS ? kTpTile : 1];
+    __shared__ int32_t hist[kTpSub], start[kTpSub];
+    const int32_t nbig = big_buckets<1024>(bstart, nb, big_min, bk, vt, wsum);
+    const int sb = rb - 6, t = threadIdx.x;
+    for (int32_t x = blockIdx.x; x < vt[nbig]; x += gridDim.x) {
+        int32_t b;
+        int64_t e0, e1;
+        big_tile(bk, vt, nbig, x, bstart, &b, &e0, &e1);
+        const int32_t len = (int32_t)(e1 - e0), r0 = b << rb;
+        if (t < kTpSub) hist[t] = 0;
+        __syncthreads();
+        int32_t sl[4], co[4], ps[4], rk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {  // loads first, indices clamped into the tile
+            const int32_t y = t + 1024 * u;
+            const int64_t yc = e0 + (y < len ? y : len - 1);
+            sl[u] = W.tp_row[yc];
+            co[u] = PACK ? 0 : W.tp_col[yc];
+            ps[u] = POS ? W.tp_pos[yc] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            rk[u] = (t + 1024 * u < len) ? atomicAdd(&hist[(PACK ? tp_local(sl[u], rb) : sl[u] - r0) >> sb], 1) : -1;
+        __syncthreads();
+        if (t < 64) {
+            const int32_t v = hist[t];
+            int32_t incl = v;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t y = __shfl_up(incl, o, 64);
+                if (t >= o) incl += y;
+            }
+            start[t] = incl - v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (rk[u] >= 0) {
+                const int32_t y = start[(PACK ? tp_local(sl[u], rb) : sl[u] - r0) >> sb] + rk[u];
+                s_slot[y] = sl[u];
+                if (!PACK) s_col[y] = co[u];
+                if (POS) s_pos[y] = ps[u];
+            }
+        }
+        __syncthreads();
+        for (int32_t y = t; y < len; y += 1024) {
+            const int32_t g = (PACK ? tp_local(s_slot[y], rb) : s_slot[y] - r0) >> sb;
+            const int64_t q = bstart[b] + cnt[(int64_t)x * kTpSub + g] + (y - start[g]);
+            W.tp_row2[q] = s_slot[y];
+            if (!PACK) W.tp_col2[q] = s_col[y];
+            if (POS) W.tp_pos2[q] = s_pos[y];
+        }
         __syncthreads();
     }
 }
@@ -1045,10 +1251,9 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     }
 }
 
-// Passes 1b-3 (scatter, split, place) in one of their forms; S tiles per
-// part of the column scan.
+// Pass 1b (scatter) in one of its forms; S tiles per part of the column scan.
 template <bool POS, bool PACK>
-void launch_tp_sort(const Csc& A, const Work& W, const TpPlan& P, int32_t S, hipStream_t s) {
+void launch_tp_scatter(const Csc& A, const Work& W, const TpPlan& P, int32_t S, hipStream_t s) {
     const int32_t nb = (int32_t)P.nb, nseg = (int32_t)P.nseg;
     constexpr int NT = kTpScatterThreads;
     if (nb <= 256)
@@ -1057,7 +1262,24 @@ void launch_tp_sort(const Csc& A, const Work& W, const TpPlan& P, int32_t S, hip
     else
         hipLaunchKernelGGL((k_tp_scatter<POS, NT, kTpMaxBuckets, PACK>), dim3(nseg), dim3(NT), 0, s, A, W, P.rb, nb, S,
                            W.tp_off, W.tp_cnt, W.tp_bstart);
-    hipLaunchKernelGGL((k_tp_split<POS, PACK>), dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, W.tp_bstart);
+}
+
+// Passes 2 and 3 (split, place); with big, buckets of more than kBigBucket
+// entries are split by the whole grid.
+constexpr int64_t kBigBucket = (int64_t)1 << 17;
+
+template <bool POS, bool PACK>
+void launch_tp_rest(const Csc& A, const Work& W, const TpPlan& P, bool big, hipStream_t s, int cus) {
+    const int32_t nb = (int32_t)P.nb;
+    const int64_t big_min = big ? kBigBucket : INT64_MAX;
+    hipLaunchKernelGGL((k_tp_split<POS, PACK>), dim3(nb), dim3(1024), 0, s, A, W, P.rb, nb, W.tp_bstart, big_min);
+    if (big) {
+        hipLaunchKernelGGL(k_tp_big_count<PACK>, dim3(cus * 4), dim3(256), 0, s, W, P.rb, nb, W.tp_bstart, big_min,
+                           W.tp_bigcnt);
+        hipLaunchKernelGGL(k_tp_big_scan, dim3(cus), dim3(1024), 0, s, W, nb, W.tp_bstart, big_min, W.tp_bigcnt);
+        hipLaunchKernelGGL((k_tp_big_scatter<POS, PACK>), dim3(cus * 2), dim3(1024), 0, s, A, W, P.rb, nb,
+                           W.tp_bstart, big_min, W.tp_bigcnt);
+    }
     hipLaunchKernelGGL((k_tp_place<POS, PACK>), dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
 }
 
@@ -1075,11 +1297,24 @@ hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions,
     // a slot's offset in its bucket and a column share one word when they fit
     const bool pack = (int64_t)A.n <= ((int64_t)1 << (32 - P.rb));
     if (positions) {
-        if (pack) launch_tp_sort<true, true>(A, W, P, S, s);
-        else launch_tp_sort<true, false>(A, W, P, S, s);
+        if (pack) launch_tp_scatter<true, true>(A, W, P, S, s);
+        else launch_tp_scatter<true, false>(A, W, P, S, s);
     } else {
-        if (pack) launch_tp_sort<false, true>(A, W, P, S, s);
-        else launch_tp_sort<false, false>(A, W, P, S, s);
+        if (pack) launch_tp_scatter<false, true>(A, W, P, S, s);
+        else launch_tp_scatter<false, false>(A, W, P, S, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_transpose_rest(const Csc& A, const Work& W, bool positions, bool big, hipStream_t s, int cus) {
+    const TpPlan P = tp_plan(A.n, A.nnz);
+    const bool pack = (int64_t)A.n <= ((int64_t)1 << (32 - P.rb));
+    if (positions) {
+        if (pack) launch_tp_rest<true, true>(A, W, P, big, s, cus);
+        else launch_tp_rest<true, false>(A, W, P, big, s, cus);
+    } else {
+        if (pack) launch_tp_rest<false, true>(A, W, P, big, s, cus);
+        else launch_tp_rest<false, false>(A, W, P, big, s, cus);
     }
     return hipGetLastError();
 }
@@ -1132,6 +1367,7 @@ hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold,
     if (tp_plan(A.n, A.nnz).ok) {
         // also fills mrk
         if ((e = launch_transpose_buckets(A, W, positions, s, cus)) != hipSuccess) return e;
+        if ((e = launch_transpose_rest(A, W, positions, has_long, s, cus)) != hipSuccess) return e;
         return launch_rowsets(A, W, s, cus);
     } else {
         // very large matrices: counting sort with global atomics
@@ -1405,6 +1641,7 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.tp_col2 = (int32_t*)take(tpz * 4);
     W.tp_pos2 = (int32_t*)take(tpz * 4);
     W.tp_sub = (int64_t*)take(P.ok ? (size_t)(P.nb * 64 + 1) * 8 : 0);
+    W.tp_bigcnt = (int32_t*)take(P.ok ? (size_t)(P.nseg + kTpMaxBuckets) * kTpSub * 4 : 0);
     Mcm M;
     M.mc = (int32_t*)take(N * 4);
     M.mr = (int32_t*)take(N * 4);

@@ -50,6 +50,9 @@ constexpr int kSpread = 64;
 // Row lists longer than this get a hash table in global memory (column ->
 // place in the list; built once per call, after the transpose).
 constexpr int kRowSetMin = 2048;
+// Flipped rows with more entries than this get their mate columns refreshed
+// by the whole grid rather than one block.
+constexpr int32_t kHeavyRow = 4096;
 constexpr int kSpreadStride = 32;  // words between two sub-list counters
 constexpr int kCounterWords = kSpreadBase + kSlots * kSpread * kSpreadStride;
 __host__ __device__ inline int spread_word(int slot, int s) {

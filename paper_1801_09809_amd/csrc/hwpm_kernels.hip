@@ -306,6 +306,9 @@ __global__ void k_apply(Csc A, Work W, int slot, int transposed) {
             const int2 sj = W.rsl[j], sc = W.rsl[c];
             W.rsl[j] = sc;
             W.rsl[c] = sj;
+            // rows too long for one block's refresh, for the grid (rare)
+            if (sc.y > kHeavyRow) W.heavy[atomicAdd(&W.counters[slot_word(slot, kHeavy)], 1)] = j;
+            if (sj.y > kHeavyRow) W.heavy[atomicAdd(&W.counters[slot_word(slot, kHeavy)], 1)] = c;
             if (W.rtab) {
                 const int32_t tj = W.rtab[j], tc = W.rtab[c];
                 W.rtab[j] = tc;
@@ -1391,14 +1394,13 @@ hipError_t launch_transpose(const Csc& A, const Work& W, int32_t long_threshold,
 }
 
 // After the flips of a round: the entries of every row whose mate changed get
-// the new mate column (one block per flipped row; a row with more than
-// kHeavyRow entries is left to k_mrk_update_heavy, which spreads each such
-// row over a row of blocks, eight rows at a time).  In incremental mode the
-// columns of those entries are marked for the next round: a root's Step-C
-// result can change only if its own mate changed or one of its rows got a
-// new mate (every value its gains read is otherwise the same), and the
-// flipped columns themselves appear in the lists of their new rows.
-constexpr int32_t kHeavyRow = 4096;
+// the new mate column (one block per flipped row; the rows with more than
+// kHeavyRow entries, which k_apply lists, then eight at a time, each over
+// an eighth of the grid).  In incremental mode the columns of those entries are marked
+// for the next round: a root's Step-C result can change only if its own mate
+// changed or one of its rows got a new mate (every value its gains read is
+// otherwise the same), and the flipped columns themselves appear in the
+// lists of their new rows.
 
 __device__ __forceinline__ void refresh_entry(const Csc& A, const Work& W, int64_t x, int32_t m, int32_t row,
                                               int incremental, int next) {
@@ -1423,28 +1425,23 @@ __global__ __launch_bounds__(256) void k_mrk_update(Csc A, Work W, int slot, int
         const int2 rl = W.rsl[m];
         const int64_t b = rl.x;
         const int32_t len = rl.y;
-        if (len > kHeavyRow) {  // block-uniform
-            if (threadIdx.x == 0) W.heavy[atomicAdd(&W.counters[slot_word(slot, kHeavy)], 1)] = m;
-            continue;
-        }
+        if (len > kHeavyRow) continue;  // block-uniform: below
         const int32_t row = W.mc[m];  // the row now matched to m owns the list
         for (int64_t x = b + threadIdx.x; x < b + len; x += blockDim.x)
             refresh_entry(A, W, x, m, row, incremental, next);
     }
-}
-
-__global__ __launch_bounds__(256) void k_mrk_update_heavy(Csc A, Work W, int slot, int incremental) {
-    if (round_over(W)) return;
+    // the heavy rows: G groups of blocks, group g taking rows g, g + G, ...
     const int32_t nh = W.counters[slot_word(slot, kHeavy)];
-    const int next = (slot + 1) % kSlots;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    // gridDim.y rows at a time, each over a row of blocks
-    for (int32_t h = blockIdx.y; h < nh; h += gridDim.y) {
+    const int32_t G = gridDim.x >= 8 ? 8 : 1, ng = gridDim.x / G;
+    const int32_t grp = blockIdx.x % G, gb = blockIdx.x / G;
+    if (gb >= ng) return;
+    const int64_t stride = (int64_t)ng * blockDim.x;
+    for (int32_t h = grp; h < nh; h += G) {
         const int32_t m = W.heavy[h];
         const int2 rl = W.rsl[m];
         const int64_t b = rl.x, e = b + rl.y;
         const int32_t row = W.mc[m];
-        for (int64_t x = b + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < e; x += stride)
+        for (int64_t x = b + (int64_t)gb * blockDim.x + threadIdx.x; x < e; x += stride)
             refresh_entry(A, W, x, m, row, incremental, next);
     }
 }
@@ -1477,8 +1474,6 @@ hipError_t launch_round_end(const Work& W, int slot, bool listed, int32_t n, hip
 
 hipError_t launch_mrk_update(const Csc& A, const Work& W, int slot, bool incremental, hipStream_t s, int cus) {
     hipLaunchKernelGGL(k_mrk_update, dim3(cus * 4), dim3(256), 0, s, A, W, slot, incremental ? 1 : 0);
-    hipLaunchKernelGGL(k_mrk_update_heavy, dim3(cus / 2 > 0 ? cus / 2 : 1, 8), dim3(256), 0, s, A, W, slot,
-                       incremental ? 1 : 0);
     return hipGetLastError();
 }
 

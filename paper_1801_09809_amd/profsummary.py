@@ -3,8 +3,9 @@ folder, and derive the HBM traffic of a kernel from two counter passes.
 
     python -m paper_1801_09809_amd.profsummary trace RESULTS.db --command "..."
     python -m paper_1801_09809_amd.profsummary pmc --fetch FETCH.db --write WRITE.db --copy-bytes N
+    python -m paper_1801_09809_amd.profsummary issue SQ.db --kernel k_search_filter --cus 256 --xcds 8
     python -m paper_1801_09809_amd.profsummary traffic --fetch FETCH.db --write WRITE.db \
-        --kernel k_search_filter,k_search_medium --name search_stage --copy-bytes N \
+        --kernel "k_search_filter<4, 8, true, false>" --kernel k_search_medium --name search_stage --copy-bytes N \
         --source csrc/hwpm_search.hip,csrc/hwpm_device.h,csrc/hwpm_hash.h,csrc/hwpm_internal.h \
         --workload random_n1048576_d16 --probe 5 --out profiles/traffic.json
 
@@ -103,9 +104,9 @@ def _calibrated(db, counter, kernel_key, copy_bytes):
 
 
 def cmd_traffic(args) -> int:
-    """Traffic of one stage: the kernels named by --kernel (comma-separated
-    substrings), each launched once per stage; their per-dispatch averages add."""
-    keys = [k for k in args.kernel.split(",") if k]
+    """Traffic of one stage: the kernels named by --kernel (one substring
+    each), each launched once per stage; their per-dispatch averages add."""
+    keys = list(args.kernel)
     h = hashlib.sha256()
     for f in args.source.split(","):
         h.update(open(f, "rb").read())
@@ -181,6 +182,37 @@ def cmd_pmc(args) -> int:
     return 0
 
 
+def cmd_issue(args) -> int:
+    """Instruction mix of one kernel from an SQ counter pass, per wave and
+    per compute unit.  A wave64 vector instruction occupies its 16-lane SIMD
+    for 4 cycles, so a CU (4 SIMDs) issues at most one per cycle: the vector
+    instructions per CU over the kernel's cycles is the vector unit's busy
+    fraction.  GRBM_GUI_ACTIVE is summed over the XCDs."""
+    con = sqlite3.connect(args.db)
+    ct = counter_table(con)
+    name = match_kernel(ct.keys(), args.kernel)
+    d = {c: v for c, (v, _n) in ct[name].items()}
+    n = min(nn for _v, nn in ct[name].values())
+    if args.command:
+        print(f"command: {args.command}")
+    print(f"kernel: {name}")
+    print(f"dispatches: {n}; counters averaged per dispatch (summed over the chip)")
+    for c in sorted(d):
+        print(f"  {c:24s} {d[c]:14.6g}")
+    waves = d.get("SQ_WAVES", 0.0)
+    if waves:
+        for c, label in (("SQ_INSTS_VALU", "vector"), ("SQ_INSTS_SALU", "scalar"),
+                         ("SQ_INSTS_VMEM_RD", "vector memory reads")):
+            if c in d:
+                print(f"{label} instructions per wave: {d[c] / waves:.1f}")
+    if "GRBM_GUI_ACTIVE" in d and "SQ_INSTS_VALU" in d:
+        cycles = d["GRBM_GUI_ACTIVE"] / args.xcds
+        per_cu = d["SQ_INSTS_VALU"] / args.cus
+        print(f"kernel cycles (per XCD): {cycles:.0f}; vector instructions per CU: {per_cu:.0f}; "
+              f"vector issue busy: {per_cu / cycles:.2f}")
+    return 0
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -191,7 +223,8 @@ def main(argv=None) -> int:
     r = sub.add_parser("traffic")
     r.add_argument("--fetch", required=True, help="database of the FETCH_SIZE pass")
     r.add_argument("--write", required=True, help="database of the WRITE_SIZE pass")
-    r.add_argument("--kernel", required=True, help="comma-separated substrings, one per kernel of the stage")
+    r.add_argument("--kernel", action="append", required=True,
+                   help="a substring naming one kernel of the stage (once per kernel)")
     r.add_argument("--name", required=True, help="key of the record in the output file")
     r.add_argument("--copy-bytes", type=int, required=True, help="bytes of each calibration copy")
     r.add_argument("--source", required=True,
@@ -207,8 +240,14 @@ def main(argv=None) -> int:
     m.add_argument("--command-fetch", default="")
     m.add_argument("--command-write", default="")
     m.add_argument("--top", type=int, default=25)
+    q = sub.add_parser("issue")
+    q.add_argument("db", help="database of an SQ counter pass")
+    q.add_argument("--kernel", required=True, help="substring naming one kernel")
+    q.add_argument("--cus", type=int, default=256)
+    q.add_argument("--xcds", type=int, default=8)
+    q.add_argument("--command", default="")
     args = ap.parse_args(argv)
-    return {"trace": cmd_trace, "traffic": cmd_traffic, "pmc": cmd_pmc}[args.cmd](args)
+    return {"trace": cmd_trace, "traffic": cmd_traffic, "pmc": cmd_pmc, "issue": cmd_issue}[args.cmd](args)
 
 
 if __name__ == "__main__":

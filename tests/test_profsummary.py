@@ -98,3 +98,37 @@ def test_pmc_table(passes, capsys):
     # raw 200 KiB fetched and 20 KiB written per dispatch; calibrated 400 and 20 KiB
     assert [float(v) for v in line[:4]] == pytest.approx([0.2048, 0.02048, 0.4096, 0.02048], abs=6e-3)
     assert line[4] == "2"
+
+
+def test_traffic_of_a_two_kernel_stage(passes, tmp_path):
+    """--kernel once per kernel of the stage (a key may hold commas, as
+    template arguments do); the per-dispatch averages add."""
+    fetch, write = passes
+    src = tmp_path / "k.hip"
+    src.write_text("kernel source")
+    out = tmp_path / "traffic.json"
+    assert ps.main(["traffic", "--fetch", fetch, "--write", write, "--kernel", "k_search_chunk<4, 8>",
+                    "--kernel", "k_tp_hist", "--name", "stage", "--copy-bytes", str(1 << 20),
+                    "--source", str(src), "--out", str(out), "--workload", "wl", "--probe", "5"]) == 0
+    rec = json.loads(out.read_text())["stage"]
+    # (200 + 50) KiB fetched x2, (20 + 5) KiB written x1
+    assert rec["read_bytes_per_launch"] == pytest.approx(250.0 * 1024 * 2)
+    assert rec["write_bytes_per_launch"] == pytest.approx(25.0 * 1024)
+    assert len(rec["kernels"]) == 2
+
+
+def test_issue_summary(tmp_path, capsys):
+    """Instruction mix per wave and the vector unit's busy fraction: 100
+    waves of 300 vector instructions on 4 CUs is 7,500 per CU; over 10,000
+    cycles per die (GRBM summed over 2 dies) that is 0.75."""
+    counters = []
+    for d in (1, 2):  # two dispatches, each counter split over two rows
+        for c, v in (("SQ_WAVES", 100.0), ("SQ_INSTS_VALU", 30000.0), ("SQ_INSTS_SALU", 5000.0),
+                     ("GRBM_GUI_ACTIVE", 20000.0)):
+            counters += [("k_search_filter<4, 8, true, false>", c, d, v / 2)] * 2
+    db = _db(tmp_path / "sq.db", [("k_search_filter<4, 8, true, false>", 1000)], counters)
+    assert ps.main(["issue", db, "--kernel", "k_search_filter", "--cus", "4", "--xcds", "2"]) == 0
+    out = capsys.readouterr().out
+    assert "vector instructions per wave: 300.0" in out
+    assert "scalar instructions per wave: 50.0" in out
+    assert "vector issue busy: 0.75" in out

@@ -125,6 +125,7 @@ struct Work {
     int32_t* rtab;      // n: offset in tabs of the hash table of the row list at slot j (-1: none);
                         // moves with rsl; null when the solve keeps no tables
     int32_t* tabs;      // nnz + 64: pool of the hash tables of the long row lists (keys, then values)
+    int32_t* tab_plan;  // 3 (nnz / kRowSetMin + 2): the tables' fill plan (first units, places)
     int32_t* rowcnt;    // n: row counts, then fill cursors
     int64_t* scan_sums; // block sums of the row-count scan
     int32_t* flips;     // 4 per flipped cycle: (i, new mate j), (l, new mate c)

@@ -449,7 +449,8 @@ __global__ __launch_bounds__(256) void k_row_fill_long(Csc A, Work W) {
 
 // Slot pointers of the row lists: rsl[j] = (start, length) of the list of
 // the row matched to j.
-// Hash tables of the long row lists (filled by k_rowset_fill, see there):
+// Hash tables of the long row lists (filled by k_rowset_plan and
+// k_rowset_fill, see there):
 // the table words a list of len entries takes from the pool of nnz + 64
 // words, or -1 (short list, or no room left).
 __device__ __forceinline__ int32_t rowset_take(const Work& W, int32_t len, int64_t nnz) {
@@ -1336,28 +1337,122 @@ struct GlobalCas32 {
     __device__ int32_t operator()(int32_t* p, int32_t e, int32_t d) const { return atomicCAS(p, e, d); }
 };
 
-__global__ __launch_bounds__(256) void k_rowset_fill(Work W) {
+// The long lists' tables are filled by the whole grid in units of kRowUnit
+// (keys to clear, then entries to insert): one block lays out the units (a
+// scan over the listed rows), and every block takes a contiguous range of
+// units, finding its first list once by binary search.  The plan holds, per
+// listed row q, the first clear unit, the first insert unit (each with the
+// total after the last row) and the table's place in the pool: the inserts
+// never read the table's place from rtab, which a failed insert clears.
+constexpr int32_t kRowUnit = 2048;
+
+__device__ __forceinline__ uint32_t rowset_size(int32_t len) {
+    uint32_t size = 64;
+    while ((int32_t)size < 2 * len) size <<= 1;
+    return size;
+}
+
+__global__ __launch_bounds__(1024) void k_rowset_plan(Work W) {
+    __shared__ int32_t wsum[32], carry[2];
     const int32_t nr = W.counters[kTabRows];
-    for (int32_t q = blockIdx.x; q < nr; q += gridDim.x) {  // block-uniform
-        const int32_t j = W.medium[q];
-        const int2 rl = W.rsl[j];
-        int32_t* tab = W.tabs + W.rtab[j];
-        uint32_t size = 64;
-        while ((int32_t)size < 2 * rl.y) size <<= 1;
-        for (uint32_t x = threadIdx.x; x < size; x += blockDim.x) tab[x] = -1;
-        __threadfence();
+    int32_t* const cst = W.tab_plan;
+    int32_t* const ist = cst + (nr + 1);
+    int32_t* const toff = ist + (nr + 1);
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    if (t == 0) carry[0] = carry[1] = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < nr; base += 1024) {  // block-uniform
+        const int32_t q = base + t;
+        int32_t cu = 0, iu = 0;
+        if (q < nr) {
+            const int32_t j = W.medium[q];
+            const int32_t len = W.rsl[j].y;
+            cu = (int32_t)(rowset_size(len) / kRowUnit);
+            iu = (len + kRowUnit - 1) / kRowUnit;
+            toff[q] = W.rtab[j];
+        }
+        const int64_t v = ((int64_t)cu << 32) | (uint32_t)iu;
+        int64_t incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t x = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += x;
+        }
+        if (lane == 63) {
+            wsum[2 * wave] = (int32_t)(incl >> 32);
+            wsum[2 * wave + 1] = (int32_t)incl;
+        }
         __syncthreads();
+        int64_t pre = incl - v;
+        for (int w = 0; w < wave; ++w) pre += ((int64_t)wsum[2 * w] << 32) + wsum[2 * w + 1];
+        if (q < nr) {
+            cst[q] = carry[0] + (int32_t)(pre >> 32);
+            ist[q] = carry[1] + (int32_t)pre;
+        }
+        __syncthreads();
+        if (t == 0) {
+            for (int w = 0; w < 16; ++w) {
+                carry[0] += wsum[2 * w];
+                carry[1] += wsum[2 * w + 1];
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        cst[nr] = carry[0];
+        ist[nr] = carry[1];
+    }
+}
+
+// The last listed row whose first unit is at most u (first[0] = 0 <= u).
+__device__ __forceinline__ int32_t rowset_row_of(const int32_t* first, int32_t nr, int32_t u) {
+    int32_t lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (first[mid] <= u) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// fill = 0: clear the keys; fill = 1: insert the entries.
+__global__ __launch_bounds__(256) void k_rowset_fill(Work W, int fill) {
+    const int32_t nr = W.counters[kTabRows];
+    if (nr == 0) return;
+    const int32_t* const cst = W.tab_plan;
+    const int32_t* const ist = cst + (nr + 1);
+    const int32_t* const toff = ist + (nr + 1);
+    const int32_t* const first = fill ? ist : cst;
+    const int32_t total = first[nr];
+    const int32_t per = (total + (int32_t)gridDim.x - 1) / (int32_t)gridDim.x;
+    const int32_t u0 = (int32_t)blockIdx.x * per, u1 = u0 + per < total ? u0 + per : total;
+    if (u0 >= u1) return;
+    int32_t q = rowset_row_of(first, nr, u0);
+    for (int32_t u = u0; u < u1; ++u) {  // block-uniform
+        while (first[q + 1] <= u) ++q;
+        const int32_t j = W.medium[q];
+        int32_t* const tab = W.tabs + toff[q];
+        const int32_t off = (u - first[q]) * kRowUnit;
+        if (!fill) {
+            for (int32_t x = threadIdx.x; x < kRowUnit; x += blockDim.x) tab[off + x] = -1;
+            continue;
+        }
+        const int2 rl = W.rsl[j];
+        const uint32_t size = rowset_size(rl.y);
+        const int32_t end = off + kRowUnit < rl.y ? off + kRowUnit : rl.y;
         bool ok = true;
-        for (int32_t x = threadIdx.x; x < rl.y; x += blockDim.x)
+        for (int32_t x = off + threadIdx.x; x < end; x += blockDim.x)
             ok &= hash_insert(tab, tab + size, W.colidx[rl.x + x], x, size - 1, GlobalCas32{});
         // a list the table cannot take (impossible with a well-formed CSC)
         // keeps the binary search
-        if (__syncthreads_or(!ok) && threadIdx.x == 0) W.rtab[j] = -1;
+        if (!ok) W.rtab[j] = -1;
     }
 }
 
 hipError_t launch_rowsets(const Csc& A, const Work& W, hipStream_t s, int cus) {
-    if (W.rtab) hipLaunchKernelGGL(k_rowset_fill, dim3(cus), dim3(256), 0, s, W);
+    if (!W.rtab) return hipSuccess;
+    hipLaunchKernelGGL(k_rowset_plan, dim3(1), dim3(1024), 0, s, W);
+    hipLaunchKernelGGL(k_rowset_fill, dim3(cus * 4), dim3(256), 0, s, W, 0);
+    hipLaunchKernelGGL(k_rowset_fill, dim3(cus * 4), dim3(256), 0, s, W, 1);
     return hipGetLastError();
 }
 
@@ -1613,6 +1708,7 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.mrk = (int32_t*)take(Z * 4 + 128);
     W.rtab = (int32_t*)take(N * 4);
     W.tabs = (int32_t*)take((Z + 64) * 4);
+    W.tab_plan = (int32_t*)take((Z / kRowSetMin + 2) * 3 * 4);
     W.rowcnt = (int32_t*)take(N * 4);
     W.scan_sums = (int64_t*)take((N / 2048 + 2) * 8);
     W.flips = (int32_t*)take(N * 4 * 4 / 2 + 16);

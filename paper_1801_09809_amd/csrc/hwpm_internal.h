@@ -26,6 +26,7 @@ enum CounterWord : int {
     kTabUsed = 72,     // u64 in words 72-73: pool words taken by the row-list hash tables
     kTabRows = 74,     // row lists that got a hash table
     kColDone = 75,     // buckets whose column scan has finished (the transpose's part 2)
+    kBigSubs = 76,     // oversized sub-buckets listed for the grid-wide placement
     kSpreadBase = 128, // sub-list counters of the wave-per-root hand-off (below)
 };
 
@@ -50,6 +51,9 @@ constexpr int kSpread = 64;
 // Row lists longer than this get a hash table in global memory (column ->
 // place in the list; built once per call, after the transpose).
 constexpr int kRowSetMin = 2048;
+// Sub-buckets listed for the grid-wide placement, at most (the rest are
+// placed by one block each).
+constexpr int kMaxBigSubs = 1024;
 // Flipped rows with more entries than this get their mate columns refreshed
 // by the whole grid rather than one block.
 constexpr int32_t kHeavyRow = 4096;
@@ -149,7 +153,8 @@ struct Work {
     int32_t* tp_col2;
     int32_t* tp_pos2;
     int64_t* tp_sub;    // start of every sub-bucket (+ total)
-    int32_t* tp_bigcnt; // oversized buckets: kTpSub counts, then places, per tile
+    int32_t* tp_bigcnt; // oversized buckets (kTpSub) or sub-buckets (kSubSlots): counts, then places, per tile
+    int32_t* tp_biglist; // oversized sub-buckets (at most kMaxBigSubs)
     // batched solves (nullptr otherwise): the block of every packed column and
     // per-block flip flags / counts
     const int32_t* mat_of_col;

@@ -1131,7 +1131,7 @@ __global__ __launch_bounds__(1024) void k_tp_big_scatter(Csc A, Work W, int rb, 
 constexpr int kPlaceTile = 2048;  // entries per LDS tile (256 threads x 8)
 
 template <bool POS, bool PACK>
-__global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t nb) {
+__global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t nb, int64_t big_sub) {
     constexpr int NS = kTpMaxRows / kTpSub;  // slots per sub-bucket, at most 128
     constexpr int U = kPlaceTile / 256;
     __shared__ int32_t rc[NS], tc[NS], ts[NS];
@@ -1147,6 +1147,17 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     const int64_t len = e1 - e0;
     const bool one_tile = len <= kPlaceTile;
     const int t = threadIdx.x;
+    if (g == nb * kTpSub - 1 && t == 0) W.rowptr[A.n] = A.nnz;
+    if (len > big_sub) {  // block-uniform: the grid-wide placement takes it while its list has room
+        __shared__ int32_t s_q;
+        if (t == 0) {
+            const int32_t q = atomicAdd(&W.counters[kBigSubs], 1);
+            if (q < kMaxBigSubs) W.tp_biglist[q] = g;
+            s_q = q;
+        }
+        __syncthreads();
+        if (s_q < kMaxBigSubs) return;
+    }
     if (t < NS) rc[t] = 0;
     __syncthreads();
     int32_t key[U], col[U], pos[U], rk[U];
@@ -1195,7 +1206,6 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
                         2 * t + 1 < nr);
         }
     }
-    if (g == nb * kTpSub - 1 && t == 0) W.rowptr[A.n] = A.nnz;
     __syncthreads();
     if (one_tile) {
 #pragma unroll
@@ -1255,6 +1265,211 @@ __global__ __launch_bounds__(256) void k_tp_place(Csc A, Work W, int rb, int32_t
     }
 }
 
+// Pass 3 for oversized sub-buckets (more than big_sub entries, listed by
+// k_tp_place: the hub rows of skewed matrices, which one block would place
+// alone, tile after tile): the same placement spread over the grid, in the
+// pass-1 scheme.  The listed sub-buckets' entries are cut into kTpTile-entry
+// tiles, numbered sub-bucket by sub-bucket; each tile's slot counts go to a
+// table (kSubSlots per tile), a block per sub-bucket scans the table's
+// columns into each tile's place in each slot's list (and writes the slot
+// pointers), and the tiles are then sorted by slot in LDS and written in
+// runs.
+constexpr int kSubSlots = kTpMaxRows / kTpSub;  // slots per sub-bucket, at most 128
+
+// The listed sub-buckets and the number of the first tile of each (vt[k],
+// vt[nl] the total), built in LDS by every block of NT threads (wsum: 2 NT /
+// 64 words); returns nl.
+template <int NT>
+__device__ int32_t big_subs(const Work& W, int32_t* gk, int32_t* vt, int32_t* wsum) {
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int PER = kMaxBigSubs / NT;
+    const int32_t listed = W.counters[kBigSubs];
+    const int32_t nl = listed < kMaxBigSubs ? listed : kMaxBigSubs;
+    int32_t tiles[PER], ntile = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int32_t k = t * PER + u;
+        int32_t c = 0;
+        if (k < nl) {
+            const int32_t g = W.tp_biglist[k];
+            gk[k] = g;
+            c = (int32_t)((W.tp_sub[g + 1] - W.tp_sub[g] + kTpTile - 1) / kTpTile);
+        }
+        tiles[u] = c;
+        ntile += c;
+    }
+    int32_t incl = ntile;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t x = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += x;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int32_t pre = incl - ntile;
+    for (int w = 0; w < wave; ++w) pre += wsum[w];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int32_t k = t * PER + u;
+        if (k < nl) vt[k] = pre;
+        pre += tiles[u];
+    }
+    int32_t total = 0;
+    for (int w = 0; w < NT / 64; ++w) total += wsum[w];
+    if (t == 0) vt[nl] = total;
+    __syncthreads();
+    return nl;
+}
+
+// The listed sub-bucket of tile x, its number in the list and the tile's
+// entry range.
+__device__ __forceinline__ void sub_tile(const Work& W, const int32_t* gk, const int32_t* vt, int32_t nl, int32_t x,
+                                         int32_t* k, int32_t* g, int64_t* e0, int64_t* e1) {
+    int32_t lo = 0, hi = nl - 1;  // the last k with vt[k] <= x
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (vt[mid] <= x) lo = mid; else hi = mid - 1;
+    }
+    *k = lo;
+    *g = gk[lo];
+    const int64_t s = W.tp_sub[*g] + (int64_t)(x - vt[lo]) * kTpTile, end = W.tp_sub[*g + 1];
+    *e0 = s;
+    *e1 = s + kTpTile < end ? s + kTpTile : end;
+}
+
+// The slot of a placed word within its sub-bucket.
+template <bool PACK>
+__device__ __forceinline__ int32_t sub_key(int32_t wd, int rb, int64_t s0) {
+    const int sb = rb - 6;
+    return PACK ? (tp_local(wd, rb) & ((1 << sb) - 1)) : (int32_t)(wd - s0);
+}
+
+__device__ __forceinline__ int64_t sub_first_slot(int32_t g, int rb) {
+    return ((int64_t)(g / kTpSub) << rb) + ((int64_t)(g % kTpSub) << (rb - 6));
+}
+
+template <bool PACK>
+__global__ __launch_bounds__(256) void k_tp_sbig_count(Work W, int rb, int32_t* __restrict__ cnt) {
+    __shared__ int32_t gk[kMaxBigSubs], vt[kMaxBigSubs + 1], wsum[4], hist[kSubSlots];
+    const int32_t nl = big_subs<256>(W, gk, vt, wsum);
+    const int t = threadIdx.x;
+    for (int32_t x = blockIdx.x; x < vt[nl]; x += gridDim.x) {
+        int32_t k, g;
+        int64_t e0, e1;
+        sub_tile(W, gk, vt, nl, x, &k, &g, &e0, &e1);
+        const int64_t s0 = sub_first_slot(g, rb);
+        if (t < kSubSlots) hist[t] = 0;
+        __syncthreads();
+        for (int64_t e = e0 + t; e < e1; e += 256) atomicAdd(&hist[sub_key<PACK>(W.tp_row2[e], rb, s0)], 1);
+        __syncthreads();
+        if (t < kSubSlots) cnt[(int64_t)x * kSubSlots + t] = hist[t];
+        __syncthreads();
+    }
+}
+
+// One block per listed sub-bucket: 8 parts of its tiles per slot.  Each
+// count becomes the place of that tile's run in the sub-bucket; the slot
+// pointers (and the long lists' tables) are recorded as k_tp_place does.
+__global__ __launch_bounds__(1024) void k_tp_sbig_scan(Csc A, Work W, int rb, int32_t* __restrict__ cnt) {
+    __shared__ int32_t gk[kMaxBigSubs], vt[kMaxBigSubs + 1], wsum[16];
+    __shared__ int32_t part[8][kSubSlots], tot[kSubSlots];
+    const int32_t nl = big_subs<1024>(W, gk, vt, wsum);
+    const int t = threadIdx.x, slot = t % kSubSlots, pt = t / kSubSlots;
+    for (int32_t k = blockIdx.x; k < nl; k += gridDim.x) {  // block-uniform
+        const int32_t g = gk[k], x0 = vt[k], nt = vt[k + 1] - vt[k];
+        const int64_t e0 = W.tp_sub[g], s0 = sub_first_slot(g, rb);
+        const int64_t s1 = s0 + ((int64_t)1 << (rb - 6)) < A.n ? s0 + ((int64_t)1 << (rb - 6)) : A.n;
+        const int32_t nr = s1 > s0 ? (int32_t)(s1 - s0) : 0;
+        const int32_t per = (nt + 7) / 8;
+        const int32_t xa = x0 + (pt * per < nt ? pt * per : nt), xb = x0 + ((pt + 1) * per < nt ? (pt + 1) * per : nt);
+        int32_t run = 0;
+        for (int32_t x = xa; x < xb; ++x) run += cnt[(int64_t)x * kSubSlots + slot];
+        part[pt][slot] = run;
+        __syncthreads();
+        int32_t total = 0;  // the slot's entries (threads t < kSubSlots)
+        if (t < kSubSlots) {  // prefix over the parts
+            for (int p = 0; p < 8; ++p) {
+                const int32_t c = part[p][t];
+                part[p][t] = total;
+                total += c;
+            }
+            tot[t] = total;
+        }
+        __syncthreads();
+        wave_scan128(tot);  // the slots' starts in the sub-bucket
+        __syncthreads();
+        if (t < kSubSlots) {  // two whole waves
+            const int32_t st = tot[t];
+            if (t < nr) {
+                W.rowptr[s0 + t] = e0 + st;
+                W.rsl[s0 + t] = make_int2((int32_t)(e0 + st), total);
+            }
+            if (W.rtab) rowset_note(W, (int32_t)(s0 + t), t < nr ? rowset_take(W, total, A.nnz) : -1, t < nr);
+            for (int p = 0; p < 8; ++p) part[p][t] += st;
+        }
+        __syncthreads();
+        run = part[pt][slot];
+        for (int32_t x = xa; x < xb; ++x) {
+            const int32_t c = cnt[(int64_t)x * kSubSlots + slot];
+            cnt[(int64_t)x * kSubSlots + slot] = run;
+            run += c;
+        }
+        __syncthreads();
+    }
+}
+
+template <bool POS, bool PACK>
+__global__ __launch_bounds__(1024) void k_tp_sbig_scatter(Csc A, Work W, int rb, const int32_t* __restrict__ cnt) {
+    __shared__ int32_t gk[kMaxBigSubs], vt[kMaxBigSubs + 1], wsum[16];
+    __shared__ int32_t s_key[kTpTile], s_col[kTpTile], s_pos[POS ? kTpTile : 1];
+    __shared__ int32_t hist[kSubSlots], start[kSubSlots];
+    const int32_t nl = big_subs<1024>(W, gk, vt, wsum);
+    const int t = threadIdx.x;
+    for (int32_t x = blockIdx.x; x < vt[nl]; x += gridDim.x) {  // block-uniform
+        int32_t k, g;
+        int64_t e0, e1;
+        sub_tile(W, gk, vt, nl, x, &k, &g, &e0, &e1);
+        const int64_t s0 = sub_first_slot(g, rb), base = W.tp_sub[g];
+        const int32_t len = (int32_t)(e1 - e0);
+        if (t < kSubSlots) hist[t] = 0;
+        __syncthreads();
+        int32_t key[4], col[4], pos[4], rk[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {  // loads first, indices clamped into the tile
+            const int32_t y = t + 1024 * u;
+            const int64_t yc = e0 + (y < len ? y : len - 1);
+            const int32_t wd = W.tp_row2[yc];
+            key[u] = sub_key<PACK>(wd, rb, s0);
+            col[u] = PACK ? tp_col_of(wd, rb) : W.tp_col2[yc];
+            pos[u] = POS ? W.tp_pos2[yc] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) rk[u] = (t + 1024 * u < len) ? atomicAdd(&hist[key[u]], 1) : -1;
+        __syncthreads();
+        if (t < kSubSlots) start[t] = hist[t];
+        __syncthreads();
+        wave_scan128(start);
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            if (rk[u] >= 0) {
+                const int32_t y = start[key[u]] + rk[u];
+                s_key[y] = key[u];
+                s_col[y] = col[u];
+                if (POS) s_pos[y] = pos[u];
+            }
+        }
+        __syncthreads();
+        for (int32_t y = t; y < len; y += 1024) {
+            const int32_t kk = s_key[y];
+            const int64_t dst = base + cnt[(int64_t)x * kSubSlots + kk] + (y - start[kk]);
+            W.colidx[dst] = s_col[y];
+            if (POS) W.cscpos[dst] = s_pos[y];
+        }
+        __syncthreads();
+    }
+}
+
 // Pass 1b (scatter) in one of its forms; S tiles per part of the column scan.
 template <bool POS, bool PACK>
 void launch_tp_scatter(const Csc& A, const Work& W, const TpPlan& P, int32_t S, hipStream_t s) {
@@ -1269,8 +1484,10 @@ void launch_tp_scatter(const Csc& A, const Work& W, const TpPlan& P, int32_t S, 
 }
 
 // Passes 2 and 3 (split, place); with big, buckets of more than kBigBucket
-// entries are split by the whole grid.
+// entries are split, and sub-buckets of more than kBigSub placed, by the
+// whole grid.
 constexpr int64_t kBigBucket = (int64_t)1 << 17;
+constexpr int64_t kBigSub = (int64_t)1 << 16;
 
 template <bool POS, bool PACK>
 void launch_tp_rest(const Csc& A, const Work& W, const TpPlan& P, bool big, hipStream_t s, int cus) {
@@ -1284,7 +1501,13 @@ void launch_tp_rest(const Csc& A, const Work& W, const TpPlan& P, bool big, hipS
         hipLaunchKernelGGL((k_tp_big_scatter<POS, PACK>), dim3(cus * 2), dim3(1024), 0, s, A, W, P.rb, nb,
                            W.tp_bstart, big_min, W.tp_bigcnt);
     }
-    hipLaunchKernelGGL((k_tp_place<POS, PACK>), dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb);
+    hipLaunchKernelGGL((k_tp_place<POS, PACK>), dim3(nb * kTpSub), dim3(256), 0, s, A, W, P.rb, nb,
+                       big ? kBigSub : INT64_MAX);
+    if (big) {
+        hipLaunchKernelGGL(k_tp_sbig_count<PACK>, dim3(cus * 4), dim3(256), 0, s, W, P.rb, W.tp_bigcnt);
+        hipLaunchKernelGGL(k_tp_sbig_scan, dim3(cus), dim3(1024), 0, s, A, W, P.rb, W.tp_bigcnt);
+        hipLaunchKernelGGL((k_tp_sbig_scatter<POS, PACK>), dim3(cus * 2), dim3(1024), 0, s, A, W, P.rb, W.tp_bigcnt);
+    }
 }
 
 hipError_t launch_transpose_buckets(const Csc& A, const Work& W, bool positions, hipStream_t s, int cus) {
@@ -1732,7 +1955,8 @@ size_t workspace_layout(int32_t n, int64_t nnz, char* base, Work* out, Mcm* mcm)
     W.tp_col2 = (int32_t*)take(tpz * 4);
     W.tp_pos2 = (int32_t*)take(tpz * 4);
     W.tp_sub = (int64_t*)take(P.ok ? (size_t)(P.nb * 64 + 1) * 8 : 0);
-    W.tp_bigcnt = (int32_t*)take(P.ok ? (size_t)(P.nseg + kTpMaxBuckets) * kTpSub * 4 : 0);
+    W.tp_bigcnt = (int32_t*)take(P.ok ? (size_t)(P.nseg + kTpMaxBuckets) * (kTpMaxRows / kTpSub) * 4 : 0);
+    W.tp_biglist = (int32_t*)take(P.ok ? (size_t)kMaxBigSubs * 4 : 0);
     Mcm M;
     M.mc = (int32_t*)take(N * 4);
     M.mr = (int32_t*)take(N * 4);

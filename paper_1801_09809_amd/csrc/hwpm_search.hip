@@ -438,12 +438,14 @@ __global__ __launch_bounds__(256) void k_search_chunk(Csc A, Work W, int32_t lon
 // lane) and the row list of m_j (E columns per lane), all loads independent.
 // The tile ORs its row list into a two-word filter (one bit per 64-bit word,
 // from two fields of one hash of the column), and each probe m_i whose two bits
-// are both set is compared exactly with the whole row list, gathered once
-// into every lane of the tile; the others are certain misses.  With about 17
-// columns in a row list a miss passes the filter about 5 % of the time, so
-// on matrices whose probes mostly miss the exact comparisons shrink from
-// every pair to a few probes per wave.  Roots whose suffix or row list
-// exceeds T * E entries are handed off.
+// are both set is compared exactly with the row list: the tile's passed
+// probes are broadcast in turn and every lane compares each with its own part
+// of the list (with positions kept, a tile maximum returns the place; without
+// them only membership is needed, taken in lane masks); the others are
+// certain misses.  With about 17 columns in a row list a miss passes the
+// filter about 5 % of the time, so on matrices whose probes mostly miss the
+// exact comparisons shrink from every pair to a few probes per wave.  Roots
+// whose suffix or row list exceeds T * E entries are handed off.
 // One multiplicative hash of the column's low 24 bits (a full-rate 24-bit
 // multiply); its bits 26-31 and 20-25 pick the bits of the two filter words.
 // Columns that agree in their low 24 bits share their bits, which can only
